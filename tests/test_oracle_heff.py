@@ -1,0 +1,108 @@
+"""Pins of the two-site oracles: O-DEF (explicit P^T H P), O-BLOCK (block-sparse
+task form) and O-DAV (Davidson), against full CI and invariants."""
+import numpy as np
+import pytest
+
+from paper_2501_18263_amd import synth
+from oracle import block, davidson, explicit, fci
+
+
+@pytest.fixture(scope="module")
+def exact8():
+    p = synth.make_problem(8, 64, 1)
+    H = explicit.heff_dense(p)
+    return p, H
+
+
+def test_sector_tables_exact_fit():
+    p = synth.make_problem(8, 64, 1)
+    assert sum(p.tab_L.values()) == 64 and len(p.tab_L) == 16
+    assert synth.psi_size(p) == 4900          # = C(8,4)^2 full-CI dimension
+
+
+def test_isometries_orthonormal():
+    p = synth.make_problem(10, 32, 4)
+    for isos in (p.iso_left, p.iso_right):
+        for blocks in isos:
+            for q, m in blocks.items():
+                assert np.abs(m.T @ m - np.eye(m.shape[1])).max() < 1e-12
+
+
+def test_exact_block_spectrum_equals_fci(exact8):
+    # complete blocks (D = 64 = 4^3): H_eff restricted to the sector is H_FCI
+    p, H = exact8
+    w = np.linalg.eigvalsh(H)
+    Hf, _ = fci.hamiltonian(p.h, p.V, p.n_up, p.n_dn)
+    wf = np.linalg.eigvalsh(Hf.toarray())
+    assert np.abs(w - wf).max() < 1e-10
+
+
+@pytest.mark.parametrize("D", [8, 16, 32])
+def test_truncated_interlacing(D):
+    # variational: lambda_i(H_eff) >= lambda_i(H_FCI) (Cauchy interlacing)
+    p = synth.make_problem(8, D, 1)
+    w = np.linalg.eigvalsh(explicit.heff_dense(p))
+    wf = np.linalg.eigvalsh(fci.hamiltonian(p.h, p.V, p.n_up, p.n_dn)[0].toarray())
+    assert np.all(w >= wf[: len(w)] - 1e-10)
+
+
+def test_heff_symmetric(exact8):
+    p, H = exact8
+    assert np.abs(H - H.T).max() < 1e-12 * np.abs(H).max()
+
+
+@pytest.mark.parametrize("N,D,seed", [(6, 16, 3), (7, 32, 2), (8, 64, 1), (8, 16, 5)])
+def test_block_equals_explicit(N, D, seed):
+    p = synth.make_problem(N, D, seed)
+    H = explicit.heff_dense(p)
+    terms = block.heff_terms(p)
+    psi = synth.random_psi(p)
+    y = block.apply(p, terms, psi, strict=True)
+    y0 = H @ psi
+    assert np.linalg.norm(y - y0) <= 1e-12 * np.linalg.norm(y0)
+    d = davidson.diagonal(p, terms)
+    assert np.abs(d - np.diag(H)).max() <= 1e-12 * np.abs(H).max()
+
+
+def test_block_hermitian_n10():
+    p = synth.make_problem(10, 48, 7)
+    terms = block.heff_terms(p)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(synth.psi_size(p))
+    y = rng.standard_normal(synth.psi_size(p))
+    hx, hy = block.apply(p, terms, x), block.apply(p, terms, y)
+    assert abs(x @ hy - hx @ y) <= 1e-13 * np.linalg.norm(hx) * np.linalg.norm(y)
+
+
+def test_block_det_isometries_match_fci_rows():
+    # with 0/1 isometries every block state is one determinant, so
+    # (H_eff psi)[i] = sum_j <det_j|H|det_i> psi_j over the kept determinants
+    p = synth.make_problem(10, 24, 9, iso_kind="det")
+    terms = block.heff_terms(p)
+    psi = synth.random_psi(p)
+    y = block.apply(p, terms, psi)
+    from oracle import detbasis
+    dets = detbasis.psi_determinants(p)
+    order = np.lexsort((dets[:, 0], dets[:, 1]))
+    basis = dets[order]
+    xs = psi[order]
+    rng = np.random.default_rng(1)
+    for i in rng.choice(len(psi), 40, replace=False):
+        ref = fci.row_dot(p.h, p.V, dets[i], basis, xs)
+        assert abs(y[i] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_davidson_reaches_fci(exact8):
+    p, H = exact8
+    terms = block.heff_terms(p)
+    d = davidson.diagonal(p, terms)
+    dav = davidson.Davidson(lambda v: H @ v, d, synth.random_psi(p))
+    for _ in range(400):
+        dav.step()
+        if dav.converged:
+            break
+    assert dav.converged
+    e_fci = np.linalg.eigvalsh(H)[0]
+    assert abs(dav.theta - e_fci) <= 1e-10 * abs(e_fci)
+    V = np.stack(dav.V, 1)
+    assert np.abs(V.T @ V - np.eye(V.shape[1])).max() < 1e-12
