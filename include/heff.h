@@ -1,0 +1,142 @@
+/*
+ * heff.h -- C ABI of the two-site effective-Hamiltonian library for
+ * MI355X (gfx950).
+ *
+ * The library implements the Davidson matrix-vector product of two-site
+ * ab initio DMRG, Psi' = H_eff Psi, in the U(1)xU(1) block-sparse task form
+ * of Sec. II.C (Eqs. ``Hamilton_act_nonsym`` and ``Hamilton_act_U1sym``):
+ * the Hamiltonian of Eq. ``Hamiltonian`` is factorized over the left block
+ * L, the two middle sites and the right block R, and every task adds
+ * f * O^L{p_L} Psi{p} O^R{p_R}^T to one output block.
+ *
+ * Conventions shared with the input generator (``synth.py``):
+ *   - N spatial orbitals, sites 0..N-1; the two-site pair is (k0, k0+1) with
+ *     k0 = N/2 - 1 (integer division); L = sites 0..k0-1, R = k0+2..N-1.
+ *   - Site state s = 0..3 is (empty, down, up, up+down) with
+ *     |up down> = c+_up c+_down |0>, label (n_up, n_dn).
+ *   - Integrals: h[i*N + j] = h_ij (symmetric); V[((i*N+j)*N+k)*N+l] =
+ *     (ij|kl) (8-fold symmetric); H = sum h_ij c+_is c_js
+ *     + 1/2 sum (ij|kl) c+_is c+_kt c_lt c_js.
+ *   - A bond table lists the sectors (n_up, n_dn) of one block, sorted
+ *     lexicographically, with their kept dimensions (> 0).
+ *   - Isometries: for every out-sector q of the new bond (in table order) a
+ *     row-major matrix with sum_s D_old(q - q(s)) rows stacked in the order
+ *     s = 0..3 and D_new(q) orthonormal columns; out-sectors concatenated.
+ *     Left site l maps (left block of l sites) x (site l) to the left block
+ *     of l+1 sites; right site N-m maps (site N-m) x (right block of m-1
+ *     sites) to the right block of m sites.
+ *   - Two-site vector layout: row-major blocks D_L(qa) x D_R(qb) for all
+ *     (qa, s_k, s_k1) in the order (index of qa, s_k, s_k1) such that
+ *     qb = (n_up, n_dn) - qa - q(s_k) - q(s_k1) is a sector of R;
+ *     concatenated without padding.  heff_psi_layout() returns it.
+ *
+ * Error behaviour: every function returns 0 (HEFF_OK) or a negative code;
+ * no exception crosses the ABI; heff_last_error() describes the last
+ * failure on a context.  Device pointers must be allocated on the context's
+ * device; all device work is enqueued on the context's stream.
+ */
+#ifndef HEFF_H
+#define HEFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct heff_ctx heff_ctx;
+typedef struct heff_blocks heff_blocks;
+typedef struct heff_dav heff_dav;
+
+enum heff_status {
+  HEFF_OK = 0,
+  HEFF_EINVAL = -1,   /* bad argument, shape, symmetry or layout             */
+  HEFF_ESECTOR = -2,  /* the target (n_up, n_dn) sector is empty             */
+  HEFF_ENOMEM = -3,   /* device or host allocation failed                     */
+  HEFF_EHIP = -4,     /* a HIP runtime call failed                            */
+  HEFF_ENOTSUP = -5,  /* precision not built for these blocks                 */
+  HEFF_ENOCONV = -6,  /* Davidson breakdown (non-finite or zero correction)   */
+  HEFF_ESTATE = -7    /* call out of order (e.g. step after convergence)      */
+};
+
+/* Arithmetic of the H_eff product (the rest of the path is FP64). */
+enum heff_prec {
+  HEFF_FP64 = 0,      /* FP64 operands, FP64 MFMA                             */
+  HEFF_FP32 = 1,      /* FP32 operands and accumulation                       */
+  HEFF_BF16X3 = 2     /* bf16 hi+lo split: hi*hi + hi*lo + lo*hi, FP32 accum. */
+};
+
+typedef struct {
+  int32_t n_sect;
+  const int32_t* nup;  /* [n_sect] host, block particle numbers (up)   */
+  const int32_t* ndn;  /* [n_sect] host                                */
+  const int32_t* dim;  /* [n_sect] host, kept dimension, > 0           */
+} heff_bond;
+
+typedef struct {
+  int32_t n_orb, n_up, n_dn;   /* N >= 4 orbitals, target sector           */
+  const double* h;             /* [N*N] host                               */
+  const double* V;             /* [N^4] host                               */
+  const heff_bond* left;       /* [k0+1]: left block with l = 0..k0 sites  */
+  const heff_bond* right;      /* [N-k0-1]: right block with m = 0..N-k0-2 */
+  const double* const* iso_left;   /* [k0] host arrays (site l builds l+1) */
+  const double* const* iso_right;  /* [N-k0-2] host, entry m-1 builds m    */
+} heff_problem;
+
+/* Context bound to HIP device `device` and stream `stream` (a hipStream_t,
+ * NULL = the null stream).  One context per host thread. */
+int heff_create(heff_ctx** ctx, int device, void* stream);
+int heff_destroy(heff_ctx* ctx);
+/* Description of the last error on ctx; valid until the next call on it. */
+const char* heff_last_error(const heff_ctx* ctx);
+
+/* Renormalized operators of L and R (the Ren_l / Ren_r recursion over all
+ * isometries), the complementary-operator sums and the task table of the
+ * two-site product (Sec. II.C).  All inputs are host memory read during
+ * the call.  prec_mask: bit (1 << HEFF_FP32) and/or (1 << HEFF_BF16X3)
+ * also prepare the reduced-precision operand copies.  Validates symmetry
+ * of h and V (1e-12), sorted non-empty bond tables consistent with the
+ * isometry shapes and orthonormal isometry columns (1e-10).  Synchronizes
+ * the context stream.  *out is owned by the caller (heff_blocks_free). */
+int heff_build_blocks(heff_ctx* ctx, const heff_problem* prob, uint32_t prec_mask,
+                      heff_blocks** out);
+int heff_blocks_free(heff_blocks* b);
+
+/* Two-site layout: number of elements and blocks; blk_desc[6*i..] =
+ * (qa_up, qa_dn, s_k, s_k1, rows, cols), blk_off[i] = element offset.
+ * Arrays are owned by `b`. */
+int heff_psi_layout(const heff_blocks* b, int64_t* n_elem, int32_t* n_blk,
+                    const int32_t** blk_desc, const int64_t** blk_off);
+
+/* Task-table statistics: tasks per product, algorithmic flops per product
+ * (sum over tasks of the cheaper contraction order), algorithmic bytes per
+ * product for FP64 / FP32 / BF16X3 operands (each referenced operator
+ * block read once + Psi read + Psi' written). bytes may be NULL. */
+int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* flops, double* bytes3);
+
+/* out = H_eff psi.  psi, out: device arrays of n_elem elements of the
+ * precision's storage type (double for FP64, float for FP32 and BF16X3);
+ * they must not alias.  Asynchronous on the context stream. */
+int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out);
+
+/* diag[i] = H_eff[i,i] (device, n_elem doubles).  Asynchronous. */
+int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag);
+
+/* Davidson eigensolver for the lowest eigenpair of H_eff (the Diag_H step).
+ * m_max in [3, 29] basis vectors, restart to {Ritz vector, previous Ritz
+ * vector}; converged when ||r|| <= tol*|theta|.  psi0: device, n_elem
+ * doubles (copied).  Basis, orthogonalization, subspace eigenproblem and
+ * Ritz vector are FP64 on the device; only the product uses `prec`. */
+int heff_dav_create(heff_ctx* ctx, const heff_blocks* b, int32_t m_max, double tol,
+                    const double* psi0, heff_dav** out);
+/* One product plus update.  Returns the Ritz value and residual norm on
+ * the host (synchronizes the stream).  HEFF_ESTATE after convergence. */
+int heff_davidson_step(heff_ctx* ctx, heff_dav* d, int prec, double* theta, double* resid);
+/* Current Ritz vector (device, n_elem doubles, largest |entry| positive). */
+int heff_dav_ritz(heff_ctx* ctx, heff_dav* d, double* psi);
+int heff_dav_free(heff_dav* d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEFF_H */

@@ -1,0 +1,1390 @@
+// Host runtime of the two-site H_eff library: problem validation, sector
+// tables, renormalized operator stores, the factorized term list and the
+// block task tables (Sec. II.C, Eqs. Hamilton_act_nonsym / _U1sym).
+//
+// Operator algebra (mode m = 2*site + spin, spin 0 = up, 1 = down):
+//   H = sum t_pq a+_p a_q + 1/2 sum g_pqrs a+_p a+_q a_s a_r,
+//   t_pq = h[i_p][i_q] d(s_p,s_q),  g_pqrs = (i_p i_r | i_q i_s) d(s_p,s_r) d(s_q,s_s).
+// Split X | Y (all X modes before Y modes, products written X-op then Y-op):
+//   H = H_X + H_Y + sum_{p in X} (a+_p S^Y_p - a_p S^Y+_p)
+//       + sum_{r in Y} (T^X_r a_r - T^X+_r a+_r)
+//       + sum_{p<q in X} (A_pq P_pq + h.c.) + sum_{p,r in X} B_pr Q_pr
+//   S^Y_p = sum_q t_pq a_q + sum g_pqrs a+_q a_s a_r   (q,r,s in Y)
+//   T^X_r = sum g_pqrs a+_p a+_q a_s                    (p,q,s in X)
+//   A_pq = a+_p a+_q,  P_pq = sum_{r,s in Y} g_pqrs a_s a_r
+//   B_pr = a+_p a_r,   Q_pr = sum_{q,s in Y} (g_pqrs - g_pqsr) a+_q a_s
+// The left block keeps a+_p, A_pq, B_pq, T_x (x outside L) and H_L; the
+// right block keeps a_r, a_s a_r, a+_q a_s, S_x (x outside R) and H_R.
+// A product l (x) m (x) r acting on |l>|mid>|r> carries
+// (-1)^(|m| n(l) + |r| (n(l) + n(mid))) for the input particle numbers.
+#include "heff_internal.h"
+#include "../../include/heff.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <set>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace heff {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HCHECK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw Error(HEFF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(HEFF_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+template <typename T>
+static void upload(DevBuf& d, const std::vector<T>& v, hipStream_t s) {
+  d.alloc(v.size() * sizeof(T));
+  if (!v.empty()) HCHECK(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------ sectors
+static const int SQU[4] = {0, 0, 1, 1};  // site state (0, dn, up, updn): n_up
+static const int SQD[4] = {0, 1, 0, 1};  //                                n_dn
+static inline int site_n(int s) { return SQU[s] + SQD[s]; }
+
+struct Bond {
+  std::vector<int> nu, nd, dim;
+  std::map<std::pair<int, int>, int> index;
+  int n() const { return (int)dim.size(); }
+  int find(int u, int d) const {
+    auto it = index.find({u, d});
+    return it == index.end() ? -1 : it->second;
+  }
+  int par(int i) const { return (nu[i] + nd[i]) & 1; }
+};
+
+static Bond make_bond(const heff_bond& b, const char* what) {
+  Bond r;
+  if (b.n_sect <= 0 || !b.nup || !b.ndn || !b.dim) throw Error(HEFF_EINVAL, std::string(what) + ": empty table");
+  for (int i = 0; i < b.n_sect; ++i) {
+    if (b.dim[i] <= 0) throw Error(HEFF_EINVAL, std::string(what) + ": non-positive dimension");
+    if (b.dim[i] > kMaxDim)
+      throw Error(HEFF_EINVAL, std::string(what) + ": sector dimension above " + std::to_string(kMaxDim));
+    if (i > 0 && std::make_pair(b.nup[i - 1], b.ndn[i - 1]) >= std::make_pair(b.nup[i], b.ndn[i]))
+      throw Error(HEFF_EINVAL, std::string(what) + ": sectors not strictly sorted");
+    r.nu.push_back(b.nup[i]);
+    r.nd.push_back(b.ndn[i]);
+    r.dim.push_back(b.dim[i]);
+    r.index[{b.nup[i], b.ndn[i]}] = i;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ integrals
+struct Ints {
+  int n = 0;
+  std::vector<double> h, V;
+  double t(int p, int q) const {
+    if ((p & 1) != (q & 1)) return 0.0;
+    return h[(size_t)(p >> 1) * n + (q >> 1)];
+  }
+  double g(int p, int q, int r, int s) const {
+    if ((p & 1) != (r & 1) || (q & 1) != (s & 1)) return 0.0;
+    int ip = p >> 1, ir = r >> 1, iq = q >> 1, is = s >> 1;
+    return V[(((size_t)ip * n + ir) * n + iq) * n + is];
+  }
+};
+
+// ------------------------------------------------------------------ site matrices
+using Mat4 = std::array<double, 16>;   // [out*4 + in]
+using Mat16 = std::array<double, 256>; // [out*16 + in], middle state 4*s_k + s_k1
+
+static Mat4 m4zero() { Mat4 m{}; return m; }
+static Mat4 m4eye() { Mat4 m{}; for (int i = 0; i < 4; ++i) m[i * 5] = 1.0; return m; }
+static Mat4 m4mul(const Mat4& a, const Mat4& b) {
+  Mat4 c{};
+  for (int i = 0; i < 4; ++i)
+    for (int k = 0; k < 4; ++k)
+      if (a[i * 4 + k] != 0.0)
+        for (int j = 0; j < 4; ++j) c[i * 4 + j] += a[i * 4 + k] * b[k * 4 + j];
+  return c;
+}
+static Mat4 m4t(const Mat4& a) { Mat4 c{}; for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) c[i * 4 + j] = a[j * 4 + i]; return c; }
+static void m4axpy(Mat4& y, double a, const Mat4& x) { for (int i = 0; i < 16; ++i) y[i] += a * x[i]; }
+static bool m4nz(const Mat4& a) { for (double v : a) if (v != 0.0) return true; return false; }
+
+static Mat4 CDAG4(int spin) {  // basis (0, dn, up, updn), |updn> = c+_up c+_dn |0>
+  Mat4 m{};
+  if (spin == 0) { m[2 * 4 + 0] = 1.0; m[3 * 4 + 1] = 1.0; }
+  else { m[1 * 4 + 0] = 1.0; m[3 * 4 + 2] = -1.0; }
+  return m;
+}
+static Mat4 C4(int spin) { return m4t(CDAG4(spin)); }
+
+static Mat16 m16zero() { Mat16 m{}; return m; }
+static Mat16 m16eye() { Mat16 m{}; for (int i = 0; i < 16; ++i) m[i * 17] = 1.0; return m; }
+static Mat16 m16mul(const Mat16& a, const Mat16& b) {
+  Mat16 c{};
+  for (int i = 0; i < 16; ++i)
+    for (int k = 0; k < 16; ++k)
+      if (a[i * 16 + k] != 0.0)
+        for (int j = 0; j < 16; ++j) c[i * 16 + j] += a[i * 16 + k] * b[k * 16 + j];
+  return c;
+}
+static Mat16 m16t(const Mat16& a) { Mat16 c{}; for (int i = 0; i < 16; ++i) for (int j = 0; j < 16; ++j) c[i * 16 + j] = a[j * 16 + i]; return c; }
+static void m16axpy(Mat16& y, double a, const Mat16& x) { for (int i = 0; i < 256; ++i) y[i] += a * x[i]; }
+static bool m16nz(const Mat16& a) { for (double v : a) if (v != 0.0) return true; return false; }
+static Mat16 kron44(const Mat4& a, const Mat4& b) {
+  Mat16 c{};
+  for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j)
+    for (int k = 0; k < 4; ++k) for (int l = 0; l < 4; ++l)
+      c[(i * 4 + k) * 16 + (j * 4 + l)] = a[i * 4 + j] * b[k * 4 + l];
+  return c;
+}
+
+// parity of a site / middle operator from its first non-zero entry
+static int par4(const Mat4& o) {
+  for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) if (o[i * 4 + j] != 0.0) return (site_n(i) + site_n(j)) & 1;
+  return 0;
+}
+static int mid_n(int m) { return site_n(m >> 2) + site_n(m & 3); }
+static int par16(const Mat16& o) {
+  for (int i = 0; i < 16; ++i) for (int j = 0; j < 16; ++j) if (o[i * 16 + j] != 0.0) return (mid_n(i) + mid_n(j)) & 1;
+  return 0;
+}
+
+// sector change of one creation (+1) / annihilation (-1) of mode m
+struct DQ { int u = 0, d = 0; };
+static inline DQ mdq(int m, int sgn) { DQ q; if ((m & 1) == 0) q.u = sgn; else q.d = sgn; return q; }
+static inline DQ operator+(DQ a, DQ b) { return {a.u + b.u, a.d + b.d}; }
+static inline DQ operator-(DQ a, DQ b) { return {a.u - b.u, a.d - b.d}; }
+static inline DQ operator-(DQ a) { return {-a.u, -a.d}; }
+
+// ------------------------------------------------------------------ operator stores
+struct Layout {
+  DQ dq;
+  std::vector<int> qin, qout, rows, cols;
+  std::vector<int64_t> off;
+  std::vector<int> blk_in, blk_out;  // sector index -> block index or -1
+  int64_t size = 0;
+};
+
+static Layout make_layout(const Bond& b, DQ dq) {
+  Layout L;
+  L.dq = dq;
+  L.blk_in.assign(b.n(), -1);
+  L.blk_out.assign(b.n(), -1);
+  for (int i = 0; i < b.n(); ++i) {
+    int o = b.find(b.nu[i] + dq.u, b.nd[i] + dq.d);
+    if (o < 0) continue;
+    L.blk_in[i] = (int)L.qin.size();
+    L.blk_out[o] = (int)L.qin.size();
+    L.qin.push_back(i);
+    L.qout.push_back(o);
+    L.rows.push_back(b.dim[o]);
+    L.cols.push_back(b.dim[i]);
+    L.off.push_back(L.size);
+    L.size += (int64_t)b.dim[o] * b.dim[i];
+  }
+  return L;
+}
+
+struct Key {
+  int kind, i, j, k;
+  bool operator<(const Key& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (i != o.i) return i < o.i;
+    if (j != o.j) return j < o.j;
+    return k < o.k;
+  }
+};
+enum Kind { K_H, K_C, K_A, K_B, K_T, K_D, K_DD, K_BB, K_S, K_TMP };
+
+struct OpId {
+  int cls = -1, idx = -1;
+  bool valid() const { return cls >= 0; }
+};
+
+struct Store {
+  const Bond* bond = nullptr;
+  std::vector<Layout> cls;
+  std::map<std::pair<int, int>, int> cls_of;
+  std::vector<std::vector<Key>> keys;   // per class, per op
+  std::vector<std::vector<int>> par;    // per class, per op
+  std::vector<int64_t> base;
+  int64_t total = 0;
+  DevBuf dev;
+  std::map<Key, OpId> names;
+
+  int class_for(DQ dq) {
+    auto it = cls_of.find({dq.u, dq.d});
+    if (it != cls_of.end()) return it->second;
+    int c = (int)cls.size();
+    cls.push_back(make_layout(*bond, dq));
+    keys.emplace_back();
+    par.emplace_back();
+    cls_of[{dq.u, dq.d}] = c;
+    return c;
+  }
+  OpId add(const Key& k, DQ dq, int parity) {
+    int c = class_for(dq);
+    OpId id{c, (int)keys[c].size()};
+    keys[c].push_back(k);
+    par[c].push_back(parity);
+    names[k] = id;
+    return id;
+  }
+  OpId get(const Key& k) const {
+    auto it = names.find(k);
+    return it == names.end() ? OpId{} : it->second;
+  }
+  void allocate(hipStream_t s, bool zero) {
+    base.assign(cls.size(), 0);
+    total = 0;
+    for (size_t c = 0; c < cls.size(); ++c) {
+      base[c] = total;
+      total += cls[c].size * (int64_t)keys[c].size();
+    }
+    dev.alloc((size_t)std::max<int64_t>(total, 1) * sizeof(double));
+    if (zero) HCHECK(hipMemsetAsync(dev.p, 0, (size_t)std::max<int64_t>(total, 1) * sizeof(double), s));
+  }
+  int64_t offset(OpId id) const { return base[id.cls] + (int64_t)id.idx * cls[id.cls].size; }
+  const Layout& lay(OpId id) const { return cls[id.cls]; }
+  int parity(OpId id) const { return par[id.cls][id.idx]; }
+};
+
+// reference to an operator as used in a term / projection source
+struct Ref {
+  int where = -1;  // -1 identity, 0 main store, 1 temp store
+  OpId id;
+  bool trans = false;
+};
+
+// ------------------------------------------------------------------ isometries (device)
+struct Iso {
+  const Bond* old = nullptr;
+  const Bond* nw = nullptr;
+  std::vector<int64_t> qoff;                 // per new sector: offset of stacked matrix
+  std::vector<std::array<int64_t, 4>> rowoff;  // per new sector, per s: first row
+  DevBuf dev;
+  int64_t size = 0;
+  // offset of block (s, q_out) stored D_old(q_in) x D_new(q_out), or -1
+  int64_t block(int s, int qo) const {
+    int qi = old->find(nw->nu[qo] - SQU[s], nw->nd[qo] - SQD[s]);
+    if (qi < 0) return -1;
+    return qoff[qo] + rowoff[qo][s] * nw->dim[qo];
+  }
+};
+
+static void make_iso(Iso& iso, const Bond& old, const Bond& nw, const double* host, hipStream_t s,
+                     const char* what) {
+  iso.old = &old;
+  iso.nw = &nw;
+  iso.qoff.resize(nw.n());
+  iso.rowoff.resize(nw.n());
+  int64_t off = 0;
+  for (int q = 0; q < nw.n(); ++q) {
+    int64_t r = 0;
+    for (int st = 0; st < 4; ++st) {
+      iso.rowoff[q][st] = r;
+      int qi = old.find(nw.nu[q] - SQU[st], nw.nd[q] - SQD[st]);
+      if (qi >= 0) r += old.dim[qi];
+    }
+    if (r < nw.dim[q]) throw Error(HEFF_EINVAL, std::string(what) + ": more kept states than reachable states");
+    iso.qoff[q] = off;
+    // orthonormality: column norms and a few column pairs
+    const double* M = host + off;
+    int D = nw.dim[q];
+    int npair = std::min(D, 8);
+    for (int a = 0; a < D; ++a) {
+      for (int bb = 0; bb < npair; ++bb) {
+        int b2 = (a + bb * 7919) % D;
+        if (bb > 0 && b2 == a) continue;
+        if (bb == 0) b2 = a;
+        double acc = 0.0;
+        for (int64_t i = 0; i < r; ++i) acc += M[i * D + a] * M[i * D + b2];
+        double want = (a == b2) ? 1.0 : 0.0;
+        if (std::fabs(acc - want) > 1e-10)
+          throw Error(HEFF_EINVAL, std::string(what) + ": isometry columns not orthonormal");
+      }
+    }
+    off += r * D;
+  }
+  iso.size = off;
+  iso.dev.alloc((size_t)std::max<int64_t>(off, 1) * sizeof(double));
+  HCHECK(hipMemcpyAsync(iso.dev.p, host, (size_t)off * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+// ------------------------------------------------------------------ step plans
+struct Src {
+  double coef;
+  Ref x;
+  Mat4 o;
+};
+struct NewDef {
+  OpId out;
+  std::vector<Src> src;
+};
+struct LinDef {
+  int in_cls;                                 // class in the main store
+  OpId out;                                   // op in the temp store (same dq)
+  std::vector<std::pair<int, double>> coefs;  // (op index in in_cls, coefficient)
+};
+
+// temp ops are linear combinations of main-store ops of one class
+struct LinPlan {
+  Store* main = nullptr;
+  Store tmp;
+  std::vector<LinDef> defs;
+  Ref make(DQ dq, int parity, const std::function<double(const Key&)>& coef) {
+    auto it = main->cls_of.find({dq.u, dq.d});
+    if (it == main->cls_of.end()) return Ref{};
+    int c = it->second;
+    LinDef d;
+    d.in_cls = c;
+    for (size_t i = 0; i < main->keys[c].size(); ++i) {
+      double v = coef(main->keys[c][i]);
+      if (v != 0.0) d.coefs.push_back({(int)i, v});
+    }
+    if (d.coefs.empty()) return Ref{};
+    Key k{K_TMP, (int)defs.size(), 0, 0};
+    d.out = tmp.add(k, dq, parity);
+    defs.push_back(std::move(d));
+    Ref r;
+    r.where = 1;
+    r.id = d.out;
+    r.id = tmp.names[k];
+    return r;
+  }
+  // run all lincombs as one GEMM per class
+  void run(hipStream_t s) {
+    tmp.allocate(s, false);
+    std::map<int, std::vector<const LinDef*>> by_cls;
+    for (auto& d : defs) by_cls[d.in_cls].push_back(&d);
+    for (auto& kv : by_cls) {
+      int c = kv.first;
+      auto& v = kv.second;
+      int n_in = (int)main->keys[c].size();
+      int n_out = (int)v.size();
+      const Layout& L = main->cls[c];
+      if (L.size == 0) continue;
+      // temps of this input class are consecutive in the temp class of the same dq
+      OpId first = v.front()->out;
+      for (int i = 0; i < n_out; ++i)
+        if (v[i]->out.cls != first.cls || v[i]->out.idx != first.idx + i)
+          throw Error(HEFF_EINVAL, "internal: temp ops not contiguous");
+      std::vector<double> C((size_t)n_out * n_in, 0.0);
+      for (int i = 0; i < n_out; ++i)
+        for (auto& pc : v[i]->coefs) C[(size_t)i * n_in + pc.first] = pc.second;
+      DevBuf dC;
+      upload(dC, C, s);
+      HCHECK(launch_gemm_f64(n_out, L.size, n_in, dC.as<double>(), main->dev.as<double>() + main->base[c],
+                             tmp.dev.as<double>() + tmp.offset(first), s));
+      HCHECK(hipStreamSynchronize(s));
+    }
+  }
+};
+
+// projection tasks of one renormalization step
+struct ChainPlan {
+  std::vector<Tile> tiles;
+  std::vector<Task> tasks;
+  std::vector<Work> work;
+  void add_work_for_tiles(size_t t_begin) {
+    for (size_t t = t_begin; t < tiles.size(); ++t)
+      for (int r = 0; r < tiles[t].a; r += kRows) work.push_back({(int32_t)t, r});
+  }
+};
+
+static void run_chain(ChainPlan& P, Bases<double> b, hipStream_t s) {
+  if (P.work.empty()) return;
+  DevBuf dt, dk, dw;
+  upload(dt, P.tiles, s);
+  upload(dk, P.tasks, s);
+  upload(dw, P.work, s);
+  HCHECK(launch_chain_f64(dt.as<Tile>(), dw.as<Work>(), (int64_t)P.work.size(), dk.as<Task>(), b, s));
+  HCHECK(hipStreamSynchronize(s));
+}
+
+// Generate the tasks new[q'<-q] += sum coef * o[s',s] * sign * A_{s'}^T X[q'-s' <- q-s] A_s
+// for all new ops.  left: sign (-1)^{|o| n(q-s)}; right: (-1)^{|X| n(s)}.
+static void plan_projection(const std::vector<NewDef>& defs, Store& nw, const Store& old, const Store* tmp,
+                            const Iso& iso, bool left, ChainPlan& P) {
+  const Bond& ob = *iso.old;
+  const Bond& nb = *iso.nw;
+  for (const NewDef& d : defs) {
+    const Layout& NL = nw.lay(d.out);
+    int64_t obase = nw.offset(d.out);
+    for (size_t bi = 0; bi < NL.qin.size(); ++bi) {
+      int qo_new = NL.qout[bi], qi_new = NL.qin[bi];
+      Tile tile;
+      tile.offOut = obase + NL.off[bi];
+      tile.a = NL.rows[bi];
+      tile.e = NL.cols[bi];
+      tile.t0 = (int32_t)P.tasks.size();
+      for (const Src& sr : d.src) {
+        const Store* st = sr.x.where == 1 ? tmp : &old;
+        int xpar = sr.x.where < 0 ? 0 : st->parity(sr.x.id);
+        int opar = par4(sr.o);
+        if (bi == 0) {  // every source must carry the sector change of the new operator
+          DQ dx{};
+          if (sr.x.where >= 0) dx = sr.x.trans ? -st->lay(sr.x.id).dq : st->lay(sr.x.id).dq;
+          DQ ds{};
+          for (int k = 0; k < 16; ++k)
+            if (sr.o[k] != 0.0) { ds = DQ{SQU[k >> 2] - SQU[k & 3], SQD[k >> 2] - SQD[k & 3]}; break; }
+          DQ tot = dx + ds;
+          if (tot.u != NL.dq.u || tot.d != NL.dq.d || ((xpar + opar) & 1) != nw.parity(d.out))
+            throw Error(HEFF_EINVAL, "internal: inconsistent renormalization source");
+        }
+        for (int so = 0; so < 4; ++so) {
+          int qa = ob.find(nb.nu[qo_new] - SQU[so], nb.nd[qo_new] - SQD[so]);
+          if (qa < 0) continue;
+          for (int si = 0; si < 4; ++si) {
+            double w = sr.o[so * 4 + si];
+            if (w == 0.0) continue;
+            int qb = ob.find(nb.nu[qi_new] - SQU[si], nb.nd[qi_new] - SQD[si]);
+            if (qb < 0) continue;
+            Task t{};
+            uint32_t fl = T_TL;
+            if (sr.x.where < 0) {
+              if (qa != qb) continue;
+              fl |= T_IDX;
+            } else {
+              const Layout& XL = st->lay(sr.x.id);
+              int blk;
+              if (!sr.x.trans) {
+                blk = XL.blk_in[qb];
+                if (blk < 0 || XL.qout[blk] != qa) continue;
+              } else {
+                blk = XL.blk_in[qa];
+                if (blk < 0 || XL.qout[blk] != qb) continue;
+                fl |= T_TX;
+              }
+              t.offX = st->offset(sr.x.id) + XL.off[blk];
+              if (sr.x.where == 1) fl |= T_SELX;
+            }
+            int sgn = left ? ((opar && ob.par(qb)) ? -1 : 1) : ((xpar && (site_n(si) & 1)) ? -1 : 1);
+            t.f = sr.coef * w * sgn;
+            t.offL = iso.block(so, qo_new);
+            t.offR = iso.block(si, qi_new);
+            t.a = (uint16_t)nb.dim[qo_new];
+            t.b = (uint16_t)ob.dim[qa];
+            t.c = (uint16_t)ob.dim[qb];
+            t.e = (uint16_t)nb.dim[qi_new];
+            t.flags = fl;
+            P.tasks.push_back(t);
+          }
+        }
+      }
+      tile.t1 = (int32_t)P.tasks.size();
+      P.tiles.push_back(tile);
+    }
+  }
+  P.add_work_for_tiles(0);
+}
+
+// ------------------------------------------------------------------ block growth
+static Mat4 site_ham(const Ints& I, int u) {
+  int site[2] = {u, u + 1};
+  Mat4 H = m4zero();
+  for (int a : site) for (int b : site) m4axpy(H, I.t(a, b), m4mul(CDAG4(a & 1), C4(b & 1)));
+  for (int a : site) for (int b : site) for (int c : site) for (int d : site) {
+    double g = I.g(a, b, c, d);
+    if (g != 0.0) m4axpy(H, 0.5 * g, m4mul(m4mul(CDAG4(a & 1), CDAG4(b & 1)), m4mul(C4(d & 1), C4(c & 1))));
+  }
+  return H;
+}
+
+struct Block {
+  Bond bond;       // copy of the current bond table
+  Store store;
+};
+
+static std::unique_ptr<Block> initial_block(bool left, int nmode, hipStream_t s) {
+  auto B = std::make_unique<Block>();
+  B->bond.nu = {0};
+  B->bond.nd = {0};
+  B->bond.dim = {1};
+  B->bond.index[{0, 0}] = 0;
+  B->store.bond = &B->bond;
+  B->store.add({K_H, 0, 0, 0}, DQ{}, 0);
+  for (int x = 0; x < nmode; ++x) {
+    if (left) B->store.add({K_T, x, 0, 0}, mdq(x, +1), 1);
+    else B->store.add({K_S, x, 0, 0}, mdq(x, -1), 1);
+  }
+  B->store.allocate(s, true);
+  return B;
+}
+
+static Ref R_(const Store& st, const Key& k, bool trans = false) {
+  Ref r;
+  r.id = st.get(k);
+  if (!r.id.valid()) throw Error(HEFF_EINVAL, "internal: missing operator");
+  r.where = 0;
+  r.trans = trans;
+  return r;
+}
+static Ref RI() { return Ref{}; }
+
+// one left step: L_old (sites 0..j-1) -> L_new (sites 0..j) with site j
+static std::unique_ptr<Block> grow_left(Block& old, const Bond& nb, const Iso& iso, int j, int nmode,
+                                        const Ints& I, hipStream_t s) {
+  auto B = std::make_unique<Block>();
+  B->bond = nb;
+  B->store.bond = &B->bond;
+  Store& os = old.store;
+  Store& ns = B->store;
+  LinPlan lp;
+  lp.main = &os;
+  lp.tmp.bond = &old.bond;
+  std::vector<NewDef> defs;
+  const int u = 2 * j, dn = 2 * j + 1;
+  const int site[2] = {u, dn};
+  Mat4 I4 = m4eye();
+  auto def = [&](Key k, DQ dq, int parity) -> NewDef& {
+    NewDef d;
+    d.out = ns.add(k, dq, parity);
+    defs.push_back(d);
+    return defs.back();
+  };
+  std::vector<int> oldm;  // old modes
+  for (int m = 0; m < 2 * j; ++m) oldm.push_back(m);
+  // creators
+  for (int p : oldm) def({K_C, p, 0, 0}, mdq(p, 1), 1).src.push_back({1.0, R_(os, {K_C, p, 0, 0}), I4});
+  for (int m : site) def({K_C, m, 0, 0}, mdq(m, 1), 1).src.push_back({1.0, RI(), CDAG4(m & 1)});
+  // pairs a+_p a+_q, p < q
+  for (int p : oldm) for (int q : oldm) if (p < q)
+    def({K_A, p, q, 0}, mdq(p, 1) + mdq(q, 1), 0).src.push_back({1.0, R_(os, {K_A, p, q, 0}), I4});
+  for (int p : oldm) for (int m : site)
+    def({K_A, p, m, 0}, mdq(p, 1) + mdq(m, 1), 0).src.push_back({1.0, R_(os, {K_C, p, 0, 0}), CDAG4(m & 1)});
+  def({K_A, u, dn, 0}, mdq(u, 1) + mdq(dn, 1), 0).src.push_back({1.0, RI(), m4mul(CDAG4(0), CDAG4(1))});
+  // a+_p a_q
+  for (int p : oldm) for (int q : oldm)
+    def({K_B, p, q, 0}, mdq(p, 1) + mdq(q, -1), 0).src.push_back({1.0, R_(os, {K_B, p, q, 0}), I4});
+  for (int p : oldm) for (int m : site) {
+    def({K_B, p, m, 0}, mdq(p, 1) + mdq(m, -1), 0).src.push_back({1.0, R_(os, {K_C, p, 0, 0}), C4(m & 1)});
+    def({K_B, m, p, 0}, mdq(m, 1) + mdq(p, -1), 0).src.push_back({-1.0, R_(os, {K_C, p, 0, 0}, true), CDAG4(m & 1)});
+  }
+  for (int m : site) for (int n : site)
+    def({K_B, m, n, 0}, mdq(m, 1) + mdq(n, -1), 0).src.push_back({1.0, RI(), m4mul(CDAG4(m & 1), C4(n & 1))});
+  // T_x = sum_{p,q,s in L} g_pqxs a+_p a+_q a_s for x outside the new block
+  for (int x = 2 * j + 2; x < nmode; ++x) {
+    DQ dqx = mdq(x, 1);
+    NewDef& d = def({K_T, x, 0, 0}, dqx, 1);
+    d.src.push_back({1.0, R_(os, {K_T, x, 0, 0}), I4});
+    for (int m : site) {
+      Ref U = lp.make(dqx - mdq(m, -1), 0, [&](const Key& k) {
+        return k.kind == K_A ? I.g(k.i, k.j, x, m) - I.g(k.j, k.i, x, m) : 0.0; });
+      if (U.where >= 0) d.src.push_back({1.0, U, C4(m & 1)});
+      Ref W = lp.make(dqx - mdq(m, 1), 0, [&](const Key& k) {
+        return k.kind == K_B ? I.g(m, k.i, x, k.j) - I.g(k.i, m, x, k.j) : 0.0; });
+      if (W.where >= 0) d.src.push_back({1.0, W, CDAG4(m & 1)});
+    }
+    for (int m : site) for (int n : site) {
+      Ref Y = lp.make(dqx - mdq(m, 1) - mdq(n, -1), 1, [&](const Key& k) {
+        return k.kind == K_C ? I.g(k.i, m, x, n) - I.g(m, k.i, x, n) : 0.0; });
+      if (Y.where >= 0) d.src.push_back({1.0, Y, m4mul(CDAG4(m & 1), C4(n & 1))});
+      if (m != n) {
+        // sum_s g_{m n x s} a_s (x) a+_m a+_n, stored untransposed as sum g c_s
+        Ref Z = lp.make(-(dqx - mdq(m, 1) - mdq(n, 1)), 1, [&](const Key& k) {
+          return k.kind == K_C ? I.g(m, n, x, k.i) : 0.0; });
+        if (Z.where >= 0) { Z.trans = true; d.src.push_back({1.0, Z, m4mul(CDAG4(m & 1), CDAG4(n & 1))}); }
+      }
+    }
+    Mat4 o3 = m4zero();
+    for (int a : site) for (int b : site) for (int c : site) {
+      double g = I.g(a, b, x, c);
+      if (g != 0.0) m4axpy(o3, g, m4mul(m4mul(CDAG4(a & 1), CDAG4(b & 1)), C4(c & 1)));
+    }
+    if (m4nz(o3)) d.src.push_back({1.0, RI(), o3});
+  }
+  // H_new
+  {
+    NewDef& d = def({K_H, 0, 0, 0}, DQ{}, 0);
+    d.src.push_back({1.0, R_(os, {K_H, 0, 0, 0}), I4});
+    d.src.push_back({1.0, RI(), site_ham(I, u)});
+    for (int p : oldm) {
+      Mat4 S = m4zero();
+      for (int q : site) if (I.t(p, q) != 0.0) m4axpy(S, I.t(p, q), C4(q & 1));
+      for (int q : site) for (int r : site) for (int t : site) {
+        double g = I.g(p, q, r, t);
+        if (g != 0.0) m4axpy(S, g, m4mul(m4mul(CDAG4(q & 1), C4(t & 1)), C4(r & 1)));
+      }
+      if (!m4nz(S)) continue;
+      d.src.push_back({1.0, R_(os, {K_C, p, 0, 0}), S});
+      d.src.push_back({-1.0, R_(os, {K_C, p, 0, 0}, true), m4t(S)});
+    }
+    for (int r : site) {
+      d.src.push_back({1.0, R_(os, {K_T, r, 0, 0}), C4(r & 1)});
+      d.src.push_back({-1.0, R_(os, {K_T, r, 0, 0}, true), CDAG4(r & 1)});
+    }
+    Ref PL = lp.make(DQ{1, 1}, 0, [&](const Key& k) {
+      return k.kind == K_A ? I.g(k.i, k.j, u, dn) - I.g(k.i, k.j, dn, u) : 0.0; });
+    if (PL.where >= 0) {
+      Mat4 op = m4mul(C4(1), C4(0));
+      d.src.push_back({1.0, PL, op});
+      Ref PT = PL;
+      PT.trans = true;
+      d.src.push_back({1.0, PT, m4t(op)});
+    }
+    for (int q : site) for (int t : site) {
+      Ref QL = lp.make(mdq(t, 1) - mdq(q, 1), 0, [&](const Key& k) {
+        return k.kind == K_B ? I.g(k.i, q, k.j, t) - I.g(k.i, q, t, k.j) : 0.0; });
+      if (QL.where >= 0) d.src.push_back({1.0, QL, m4mul(CDAG4(q & 1), C4(t & 1))});
+    }
+  }
+  lp.run(s);
+  ns.allocate(s, false);
+  ChainPlan P;
+  plan_projection(defs, ns, os, &lp.tmp, iso, true, P);
+  Bases<double> b{};
+  b.L[0] = b.L[1] = iso.dev.as<double>();
+  b.R[0] = b.R[1] = iso.dev.as<double>();
+  b.X[0] = os.dev.as<double>();
+  b.X[1] = lp.tmp.dev.as<double>();
+  b.out = ns.dev.as<double>();
+  run_chain(P, b, s);
+  return B;
+}
+
+// one right step: R_old (sites j+1..N-1) -> R_new (sites j..N-1) with site j
+static std::unique_ptr<Block> grow_right(Block& old, const Bond& nb, const Iso& iso, int j, int nmode,
+                                         const Ints& I, hipStream_t s) {
+  auto B = std::make_unique<Block>();
+  B->bond = nb;
+  B->store.bond = &B->bond;
+  Store& os = old.store;
+  Store& ns = B->store;
+  LinPlan lp;
+  lp.main = &os;
+  lp.tmp.bond = &old.bond;
+  std::vector<NewDef> defs;
+  const int u = 2 * j, dn = 2 * j + 1;
+  const int site[2] = {u, dn};
+  Mat4 I4 = m4eye();
+  auto def = [&](Key k, DQ dq, int parity) -> NewDef& {
+    NewDef d;
+    d.out = ns.add(k, dq, parity);
+    defs.push_back(d);
+    return defs.back();
+  };
+  std::vector<int> oldm;
+  for (int m = 2 * j + 2; m < nmode; ++m) oldm.push_back(m);
+  // annihilators a_r
+  for (int m : site) def({K_D, m, 0, 0}, mdq(m, -1), 1).src.push_back({1.0, RI(), C4(m & 1)});
+  for (int r : oldm) def({K_D, r, 0, 0}, mdq(r, -1), 1).src.push_back({1.0, R_(os, {K_D, r, 0, 0}), I4});
+  // a_s a_r, r < s
+  def({K_DD, u, dn, 0}, mdq(u, -1) + mdq(dn, -1), 0).src.push_back({1.0, RI(), m4mul(C4(1), C4(0))});
+  for (int m : site) for (int t : oldm)
+    def({K_DD, m, t, 0}, mdq(m, -1) + mdq(t, -1), 0).src.push_back({-1.0, R_(os, {K_D, t, 0, 0}), C4(m & 1)});
+  for (int r : oldm) for (int t : oldm) if (r < t)
+    def({K_DD, r, t, 0}, mdq(r, -1) + mdq(t, -1), 0).src.push_back({1.0, R_(os, {K_DD, r, t, 0}), I4});
+  // a+_q a_s
+  for (int m : site) for (int n : site)
+    def({K_BB, m, n, 0}, mdq(m, 1) + mdq(n, -1), 0).src.push_back({1.0, RI(), m4mul(CDAG4(m & 1), C4(n & 1))});
+  for (int m : site) for (int t : oldm) {
+    def({K_BB, m, t, 0}, mdq(m, 1) + mdq(t, -1), 0).src.push_back({1.0, R_(os, {K_D, t, 0, 0}), CDAG4(m & 1)});
+    def({K_BB, t, m, 0}, mdq(t, 1) + mdq(m, -1), 0).src.push_back({-1.0, R_(os, {K_D, t, 0, 0}, true), C4(m & 1)});
+  }
+  for (int q : oldm) for (int t : oldm)
+    def({K_BB, q, t, 0}, mdq(q, 1) + mdq(t, -1), 0).src.push_back({1.0, R_(os, {K_BB, q, t, 0}), I4});
+  // S_x for x outside the new block
+  for (int x = 0; x < 2 * j; ++x) {
+    DQ dqx = mdq(x, -1);
+    NewDef& d = def({K_S, x, 0, 0}, dqx, 1);
+    d.src.push_back({1.0, R_(os, {K_S, x, 0, 0}), I4});
+    for (int m : site) {
+      if (I.t(x, m) != 0.0) d.src.push_back({I.t(x, m), RI(), C4(m & 1)});
+      Ref D = lp.make(dqx - mdq(m, 1), 0, [&](const Key& k) {
+        return k.kind == K_DD ? I.g(x, m, k.i, k.j) - I.g(x, m, k.j, k.i) : 0.0; });
+      if (D.where >= 0) d.src.push_back({1.0, D, CDAG4(m & 1)});
+      Ref Bq = lp.make(dqx - mdq(m, -1), 0, [&](const Key& k) {
+        return k.kind == K_BB ? I.g(x, k.i, m, k.j) - I.g(x, k.i, k.j, m) : 0.0; });
+      if (Bq.where >= 0) d.src.push_back({1.0, Bq, C4(m & 1)});
+    }
+    for (int m : site) for (int n : site) {
+      Ref Yd = lp.make(dqx - mdq(m, 1) - mdq(n, -1), 1, [&](const Key& k) {
+        return k.kind == K_D ? I.g(x, m, k.i, n) - I.g(x, m, n, k.i) : 0.0; });
+      if (Yd.where >= 0) d.src.push_back({1.0, Yd, m4mul(CDAG4(m & 1), C4(n & 1))});
+      if (m != n) {
+        // (q outside site; r = m, s = n): a_n a_m (x) a+_q, stored as sum g d_q
+        Ref Zd = lp.make(-(dqx - mdq(m, -1) - mdq(n, -1)), 1, [&](const Key& k) {
+          return k.kind == K_D ? I.g(x, k.i, m, n) : 0.0; });
+        if (Zd.where >= 0) { Zd.trans = true; d.src.push_back({1.0, Zd, m4mul(C4(n & 1), C4(m & 1))}); }
+      }
+    }
+    Mat4 o3 = m4zero();
+    for (int a : site) for (int b : site) for (int c : site) {
+      double g = I.g(x, a, b, c);
+      if (g != 0.0) m4axpy(o3, g, m4mul(m4mul(CDAG4(a & 1), C4(c & 1)), C4(b & 1)));
+    }
+    if (m4nz(o3)) d.src.push_back({1.0, RI(), o3});
+  }
+  // H_new
+  {
+    NewDef& d = def({K_H, 0, 0, 0}, DQ{}, 0);
+    d.src.push_back({1.0, R_(os, {K_H, 0, 0, 0}), I4});
+    d.src.push_back({1.0, RI(), site_ham(I, u)});
+    for (int p : site) {
+      d.src.push_back({1.0, R_(os, {K_S, p, 0, 0}), CDAG4(p & 1)});
+      d.src.push_back({-1.0, R_(os, {K_S, p, 0, 0}, true), C4(p & 1)});
+    }
+    for (int r : oldm) {
+      Mat4 Ts = m4zero();
+      for (int a : site) for (int b : site) for (int c : site) {
+        double g = I.g(a, b, r, c);
+        if (g != 0.0) m4axpy(Ts, g, m4mul(m4mul(CDAG4(a & 1), CDAG4(b & 1)), C4(c & 1)));
+      }
+      if (!m4nz(Ts)) continue;
+      d.src.push_back({1.0, R_(os, {K_D, r, 0, 0}), Ts});
+      d.src.push_back({-1.0, R_(os, {K_D, r, 0, 0}, true), m4t(Ts)});
+    }
+    Ref P = lp.make(DQ{-1, -1}, 0, [&](const Key& k) {
+      return k.kind == K_DD ? I.g(u, dn, k.i, k.j) - I.g(u, dn, k.j, k.i) : 0.0; });
+    if (P.where >= 0) {
+      Mat4 op = m4mul(CDAG4(0), CDAG4(1));
+      d.src.push_back({1.0, P, op});
+      Ref PT = P;
+      PT.trans = true;
+      d.src.push_back({1.0, PT, m4t(op)});
+    }
+    for (int p : site) for (int r : site) {
+      Ref Q = lp.make(mdq(r, 1) - mdq(p, 1), 0, [&](const Key& k) {
+        return k.kind == K_BB ? I.g(p, k.i, r, k.j) - I.g(p, k.i, k.j, r) : 0.0; });
+      if (Q.where >= 0) d.src.push_back({1.0, Q, m4mul(CDAG4(p & 1), C4(r & 1))});
+    }
+  }
+  lp.run(s);
+  ns.allocate(s, false);
+  ChainPlan P;
+  plan_projection(defs, ns, os, &lp.tmp, iso, false, P);
+  Bases<double> b{};
+  b.L[0] = b.L[1] = iso.dev.as<double>();
+  b.R[0] = b.R[1] = iso.dev.as<double>();
+  b.X[0] = os.dev.as<double>();
+  b.X[1] = lp.tmp.dev.as<double>();
+  b.out = ns.dev.as<double>();
+  run_chain(P, b, s);
+  return B;
+}
+
+// ------------------------------------------------------------------ the two-site terms
+struct Term {
+  double coef;
+  Ref l;    // left-block operator (where 0: L store, 1: L temps)
+  Mat16 mu; // middle-site operator
+  Ref r;    // right-block operator (where 0: R store, 1: R temps)
+};
+
+}  // namespace heff
+
+// ====================================================================== public objects
+
+struct heff_blocks {
+  heff_ctx* ctx = nullptr;
+  int n_orb = 0, n_up = 0, n_dn = 0, k0 = 0;
+  uint32_t prec_mask = 0;
+  std::unique_ptr<heff::Block> L, R;
+  heff::LinPlan Ltmp, Rtmp;
+  std::vector<heff::Term> terms;
+  // two-site layout
+  std::vector<int32_t> blk_desc;
+  std::vector<int64_t> blk_off;
+  std::vector<int> blk_qa, blk_qb;
+  std::map<std::array<int, 3>, int> blk_index;  // (qa index, s_k, s_k1) -> block
+  int64_t n_elem = 0;
+  // product task table
+  heff::DevBuf d_tiles, d_tasks, d_work, d_dtiles, d_dtasks;
+  int64_t n_tiles = 0, n_tasks = 0, n_work = 0, n_dtasks = 0;
+  double flops = 0.0, bytes[3] = {0, 0, 0};
+  // reduced-precision operand copies: [L store, L temps, R store, R temps]
+  heff::DevBuf f32[4], bhi[4], blo[4];
+};
+
+namespace heff {
+
+static Mat16 mid_c(int m, bool dag, int k0) {
+  int sp = m & 1;
+  Mat4 op = dag ? CDAG4(sp) : C4(sp);
+  Mat4 F = m4zero();
+  F[0] = 1; F[5] = -1; F[10] = -1; F[15] = 1;
+  if ((m >> 1) == k0) return kron44(op, m4eye());
+  return kron44(F, op);
+}
+
+static void add_term(std::vector<Term>& T, double c, Ref l, const Mat16& mu, Ref r, bool hc,
+                     const Store& Ls, const Store& Lt, const Store& Rs, const Store& Rt) {
+  if (c == 0.0 || !m16nz(mu)) return;
+  T.push_back({c, l, mu, r});
+  if (hc) {
+    int pl = l.where < 0 ? 0 : (l.where == 0 ? Ls : Lt).parity(l.id);
+    int pr = r.where < 0 ? 0 : (r.where == 0 ? Rs : Rt).parity(r.id);
+    int pm = par16(mu);
+    int sgn = ((pl * pm + pl * pr + pm * pr) & 1) ? -1 : 1;
+    Ref l2 = l, r2 = r;
+    if (l2.where >= 0) l2.trans = !l2.trans;
+    if (r2.where >= 0) r2.trans = !r2.trans;
+    T.push_back({c * sgn, l2, m16t(mu), r2});
+  }
+}
+
+static void build_terms(heff_blocks& B, const Ints& I) {
+  Store& Ls = B.L->store;
+  Store& Rs = B.R->store;
+  LinPlan& lt = B.Ltmp;
+  LinPlan& rt = B.Rtmp;
+  lt.main = &Ls;
+  lt.tmp.bond = &B.L->bond;
+  rt.main = &Rs;
+  rt.tmp.bond = &B.R->bond;
+  const int k0 = B.k0;
+  const int nmode = 2 * B.n_orb;
+  std::vector<int> Lm, M, Rm, X;
+  for (int m = 0; m < 2 * k0; ++m) Lm.push_back(m);
+  for (int m = 2 * k0; m < 2 * k0 + 4; ++m) M.push_back(m);
+  for (int m = 2 * k0 + 4; m < nmode; ++m) Rm.push_back(m);
+  X = Lm;
+  X.insert(X.end(), M.begin(), M.end());
+  std::map<int, Mat16> cd, cc;
+  for (int m : M) { cd[m] = mid_c(m, true, k0); cc[m] = mid_c(m, false, k0); }
+  const Mat16 I16 = m16eye();
+  std::vector<Term>& T = B.terms;
+  auto add = [&](double c, Ref l, const Mat16& mu, Ref r, bool hc) {
+    add_term(T, c, l, mu, r, hc, Ls, lt.tmp, Rs, rt.tmp);
+  };
+  auto isL = [&](int m) { return m < 2 * k0; };
+  // --- all lincombs first (temps must be created before the stores run)
+  std::map<std::pair<int, int>, Ref> PL, QL, U, W;
+  std::map<std::array<int, 3>, Ref> Y, Z;
+  std::map<std::pair<int, int>, Ref> P, Q;
+  for (size_t i = 0; i < M.size(); ++i) for (size_t k = i + 1; k < M.size(); ++k) {
+    int r = M[i], s = M[k];
+    PL[{r, s}] = lt.make(mdq(r, 1) + mdq(s, 1), 0, [&](const Key& key) {
+      return key.kind == K_A ? I.g(key.i, key.j, r, s) - I.g(key.i, key.j, s, r) : 0.0; });
+  }
+  for (int q : M) for (int s : M)
+    QL[{q, s}] = lt.make(mdq(s, 1) - mdq(q, 1), 0, [&](const Key& key) {
+      return key.kind == K_B ? I.g(key.i, q, key.j, s) - I.g(key.i, q, s, key.j) : 0.0; });
+  for (int r : Rm) {
+    DQ dqr = mdq(r, 1);
+    for (int m : M) {
+      U[{r, m}] = lt.make(dqr - mdq(m, -1), 0, [&](const Key& key) {
+        return key.kind == K_A ? I.g(key.i, key.j, r, m) - I.g(key.j, key.i, r, m) : 0.0; });
+      W[{r, m}] = lt.make(dqr - mdq(m, 1), 0, [&](const Key& key) {
+        return key.kind == K_B ? I.g(m, key.i, r, key.j) - I.g(key.i, m, r, key.j) : 0.0; });
+    }
+    for (int m : M) for (int n : M) {
+      Y[{r, m, n}] = lt.make(dqr - mdq(m, 1) - mdq(n, -1), 1, [&](const Key& key) {
+        return key.kind == K_C ? I.g(key.i, m, r, n) - I.g(m, key.i, r, n) : 0.0; });
+      if (m != n) {
+        Ref z = lt.make(-(dqr - mdq(m, 1) - mdq(n, 1)), 1, [&](const Key& key) {
+          return key.kind == K_C ? I.g(m, n, r, key.i) : 0.0; });
+        if (z.where >= 0) z.trans = true;
+        Z[{r, m, n}] = z;
+      }
+    }
+  }
+  for (size_t i = 0; i < X.size(); ++i) for (size_t k = i + 1; k < X.size(); ++k) {
+    int a = X[i], b = X[k];
+    P[{a, b}] = rt.make(-(mdq(a, 1) + mdq(b, 1)), 0, [&](const Key& key) {
+      return key.kind == K_DD ? I.g(a, b, key.i, key.j) - I.g(a, b, key.j, key.i) : 0.0; });
+  }
+  for (int a : X) for (int b : X)
+    Q[{a, b}] = rt.make(mdq(b, 1) - mdq(a, 1), 0, [&](const Key& key) {
+      return key.kind == K_BB ? I.g(a, key.i, b, key.j) - I.g(a, key.i, key.j, b) : 0.0; });
+
+  // --- H^X (x) I_R with X = L + M
+  add(1.0, R_(Ls, {K_H, 0, 0, 0}), I16, RI(), false);
+  Mat16 HM = m16zero();
+  for (int a : M) for (int b : M) if (I.t(a, b) != 0.0) m16axpy(HM, I.t(a, b), m16mul(cd[a], cc[b]));
+  for (int a : M) for (int b : M) for (int c : M) for (int d : M) {
+    double g = I.g(a, b, c, d);
+    if (g != 0.0) m16axpy(HM, 0.5 * g, m16mul(m16mul(cd[a], cd[b]), m16mul(cc[d], cc[c])));
+  }
+  add(1.0, RI(), HM, RI(), false);
+  for (int p : Lm) {
+    Mat16 S = m16zero();
+    for (int q : M) if (I.t(p, q) != 0.0) m16axpy(S, I.t(p, q), cc[q]);
+    for (int q : M) for (int r : M) for (int s : M) {
+      double g = I.g(p, q, r, s);
+      if (g != 0.0) m16axpy(S, g, m16mul(m16mul(cd[q], cc[s]), cc[r]));
+    }
+    add(1.0, R_(Ls, {K_C, p, 0, 0}), S, RI(), true);
+  }
+  for (int m : M) add(1.0, R_(Ls, {K_T, m, 0, 0}), cc[m], RI(), true);
+  for (auto& kv : PL) if (kv.second.where >= 0)
+    add(1.0, kv.second, m16mul(cc[kv.first.second], cc[kv.first.first]), RI(), true);
+  for (auto& kv : QL) if (kv.second.where >= 0)
+    add(1.0, kv.second, m16mul(cd[kv.first.first], cc[kv.first.second]), RI(), false);
+  // --- I (x) I (x) H^R
+  add(1.0, RI(), I16, R_(Rs, {K_H, 0, 0, 0}), false);
+  // --- sum_{p in X} a+_p S^R_p + h.c.
+  for (int p : Lm) add(1.0, R_(Ls, {K_C, p, 0, 0}), I16, R_(Rs, {K_S, p, 0, 0}), true);
+  for (int m : M) add(1.0, RI(), cd[m], R_(Rs, {K_S, m, 0, 0}), true);
+  // --- sum_{r in R} T^X_r a_r + h.c.
+  for (int r : Rm) {
+    Ref rho = R_(Rs, {K_D, r, 0, 0});
+    add(1.0, R_(Ls, {K_T, r, 0, 0}), I16, rho, true);
+    for (int m : M) {
+      if (U[{r, m}].where >= 0) add(1.0, U[{r, m}], cc[m], rho, true);
+      if (W[{r, m}].where >= 0) add(1.0, W[{r, m}], cd[m], rho, true);
+    }
+    for (int m : M) for (int n : M) {
+      if (Y[{r, m, n}].where >= 0) add(1.0, Y[{r, m, n}], m16mul(cd[m], cc[n]), rho, true);
+      if (m != n && Z[{r, m, n}].where >= 0) add(1.0, Z[{r, m, n}], m16mul(cd[m], cd[n]), rho, true);
+    }
+    Mat16 tau = m16zero();
+    for (int a : M) for (int b : M) for (int d : M) {
+      double g = I.g(a, b, r, d);
+      if (g != 0.0) m16axpy(tau, g, m16mul(m16mul(cd[a], cd[b]), cc[d]));
+    }
+    add(1.0, RI(), tau, rho, true);
+  }
+  // --- sum_{p<q in X} A^X_pq P^R_pq + h.c.
+  for (size_t i = 0; i < X.size(); ++i) for (size_t k = i + 1; k < X.size(); ++k) {
+    int a = X[i], b = X[k];
+    Ref Pr = P[{a, b}];
+    if (Pr.where < 0) continue;
+    if (isL(a) && isL(b)) add(1.0, R_(Ls, {K_A, a, b, 0}), I16, Pr, true);
+    else if (isL(a)) add(1.0, R_(Ls, {K_C, a, 0, 0}), cd[b], Pr, true);
+    else add(1.0, RI(), m16mul(cd[a], cd[b]), Pr, true);
+  }
+  // --- sum_{p,r in X} B^X_pr Q^R_pr
+  for (int a : X) for (int b : X) {
+    Ref Qr = Q[{a, b}];
+    if (Qr.where < 0) continue;
+    if (isL(a) && isL(b)) add(1.0, R_(Ls, {K_B, a, b, 0}), I16, Qr, false);
+    else if (isL(a)) add(1.0, R_(Ls, {K_C, a, 0, 0}), cc[b], Qr, false);
+    else if (isL(b)) add(-1.0, R_(Ls, {K_C, b, 0, 0}, true), cd[a], Qr, false);
+    else add(1.0, RI(), m16mul(cd[a], cc[b]), Qr, false);
+  }
+}
+
+// ------------------------------------------------------------------ product tasks
+static void build_psi_layout(heff_blocks& B) {
+  const Bond& bl = B.L->bond;
+  const Bond& br = B.R->bond;
+  int64_t off = 0;
+  for (int qa = 0; qa < bl.n(); ++qa)
+    for (int sk = 0; sk < 4; ++sk)
+      for (int sk1 = 0; sk1 < 4; ++sk1) {
+        int u = B.n_up - bl.nu[qa] - SQU[sk] - SQU[sk1];
+        int d = B.n_dn - bl.nd[qa] - SQD[sk] - SQD[sk1];
+        int qb = br.find(u, d);
+        if (qb < 0) continue;
+        int idx = (int)B.blk_off.size();
+        B.blk_index[{qa, sk, sk1}] = idx;
+        B.blk_desc.insert(B.blk_desc.end(), {bl.nu[qa], bl.nd[qa], sk, sk1, bl.dim[qa], br.dim[qb]});
+        B.blk_off.push_back(off);
+        B.blk_qa.push_back(qa);
+        B.blk_qb.push_back(qb);
+        off += (int64_t)bl.dim[qa] * br.dim[qb];
+      }
+  B.n_elem = off;
+  if (B.blk_off.empty()) throw Error(HEFF_ESECTOR, "no two-site block in the target sector");
+}
+
+static double task_flops(const Task& t) {
+  double a = t.a, b = t.b, c = t.c, e = t.e;
+  bool idl = t.flags & T_IDL, idr = t.flags & T_IDR;
+  if (idl && idr) return 2.0 * a * e;
+  if (idl) return 2.0 * a * c * e;
+  if (idr) return 2.0 * a * b * c;
+  return std::min(2 * a * b * c + 2 * a * c * e, 2 * b * c * e + 2 * a * b * e);
+}
+
+static void build_tasks(heff_blocks& B, hipStream_t s) {
+  const Bond& bl = B.L->bond;
+  const Bond& br = B.R->bond;
+  const Store& Ls = B.L->store;
+  const Store& Lt = B.Ltmp.tmp;
+  const Store& Rs = B.R->store;
+  const Store& Rt = B.Rtmp.tmp;
+  const int nb = (int)B.blk_off.size();
+  std::vector<std::vector<Task>> per(nb);
+  std::vector<std::vector<DiagTask>> dper(nb);
+  std::set<std::pair<int, int64_t>> seen;  // referenced operator blocks (store id, offset)
+  double op_elems = 0.0;
+  for (const Term& tm : B.terms) {
+    const Store* lst = tm.l.where < 0 ? nullptr : (tm.l.where == 0 ? &Ls : &Lt);
+    const Store* rst = tm.r.where < 0 ? nullptr : (tm.r.where == 0 ? &Rs : &Rt);
+    int pm = par16(tm.mu);
+    int pr = rst ? rst->parity(tm.r.id) : 0;
+    for (int x = 0; x < nb; ++x) {
+      int qa = B.blk_qa[x], qb = B.blk_qb[x];
+      int sk = B.blk_desc[6 * x + 2], sk1 = B.blk_desc[6 * x + 3];
+      int mid = 4 * sk + sk1;
+      // left block
+      int qa2 = qa, lblk = -1;
+      if (lst) {
+        const Layout& LL = lst->lay(tm.l.id);
+        if (!tm.l.trans) { lblk = LL.blk_in[qa]; if (lblk < 0) continue; qa2 = LL.qout[lblk]; }
+        else { lblk = LL.blk_out[qa]; if (lblk < 0) continue; qa2 = LL.qin[lblk]; }
+      }
+      int qb2 = qb, rblk = -1;
+      if (rst) {
+        const Layout& RL = rst->lay(tm.r.id);
+        if (!tm.r.trans) { rblk = RL.blk_in[qb]; if (rblk < 0) continue; qb2 = RL.qout[rblk]; }
+        else { rblk = RL.blk_out[qb]; if (rblk < 0) continue; qb2 = RL.qin[rblk]; }
+      }
+      int nl = bl.par(qa), nmid = mid_n(mid) & 1;
+      int sgn = ((pm * nl + pr * (nl + nmid)) & 1) ? -1 : 1;
+      for (int mid2 = 0; mid2 < 16; ++mid2) {
+        double w = tm.mu[mid2 * 16 + mid];
+        if (w == 0.0) continue;
+        auto it = B.blk_index.find({qa2, mid2 >> 2, mid2 & 3});
+        if (it == B.blk_index.end()) continue;
+        int y = it->second;
+        if (B.blk_qb[y] != qb2) throw Error(HEFF_EINVAL, "internal: term violates sector conservation");
+        Task t{};
+        t.f = tm.coef * w * sgn;
+        t.a = (uint16_t)bl.dim[qa2];
+        t.b = (uint16_t)bl.dim[qa];
+        t.c = (uint16_t)br.dim[qb];
+        t.e = (uint16_t)br.dim[qb2];
+        t.offX = B.blk_off[x];
+        uint32_t fl = 0;
+        if (!lst) fl |= T_IDL;
+        else {
+          t.offL = lst->offset(tm.l.id) + lst->lay(tm.l.id).off[lblk];
+          if (tm.l.trans) fl |= T_TL;
+          if (tm.l.where == 1) fl |= T_SELL;
+          if (seen.insert({tm.l.where, t.offL}).second) op_elems += (double)t.a * t.b;
+        }
+        if (!rst) fl |= T_IDR;
+        else {
+          t.offR = rst->offset(tm.r.id) + rst->lay(tm.r.id).off[rblk];
+          if (!tm.r.trans) fl |= T_TR;
+          if (tm.r.where == 1) fl |= T_SELR;
+          if (seen.insert({2 + tm.r.where, t.offR}).second) op_elems += (double)t.c * t.e;
+        }
+        t.flags = fl;
+        per[y].push_back(t);
+        B.flops += task_flops(t);
+        if (mid2 == mid && qa2 == qa && qb2 == qb) {
+          DiagTask dt{};
+          dt.f = t.f;
+          dt.flags = fl & (T_IDL | T_IDR | T_SELL | T_SELR);
+          dt.offL = t.offL;
+          dt.offR = t.offR;
+          dper[y].push_back(dt);
+        }
+      }
+    }
+  }
+  std::vector<Tile> tiles(nb), dtiles(nb);
+  std::vector<Task> tasks;
+  std::vector<DiagTask> dtasks;
+  std::vector<Work> work;
+  for (int y = 0; y < nb; ++y) {
+    Tile t;
+    t.offOut = B.blk_off[y];
+    t.a = B.blk_desc[6 * y + 4];
+    t.e = B.blk_desc[6 * y + 5];
+    t.t0 = (int32_t)tasks.size();
+    tasks.insert(tasks.end(), per[y].begin(), per[y].end());
+    t.t1 = (int32_t)tasks.size();
+    tiles[y] = t;
+    Tile d = t;
+    d.t0 = (int32_t)dtasks.size();
+    dtasks.insert(dtasks.end(), dper[y].begin(), dper[y].end());
+    d.t1 = (int32_t)dtasks.size();
+    dtiles[y] = d;
+  }
+  // largest output blocks first (longest work items start early)
+  std::vector<int> order(nb);
+  for (int i = 0; i < nb; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    double wa = 0, wb = 0;
+    for (int k = tiles[a].t0; k < tiles[a].t1; ++k) wa += task_flops(tasks[k]) / std::max(1, tiles[a].a);
+    for (int k = tiles[b].t0; k < tiles[b].t1; ++k) wb += task_flops(tasks[k]) / std::max(1, tiles[b].a);
+    return wa > wb;
+  });
+  for (int y : order)
+    for (int r = 0; r < tiles[y].a; r += kRows) work.push_back({y, r});
+  if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
+  B.n_tiles = nb;
+  B.n_tasks = (int64_t)tasks.size();
+  B.n_work = (int64_t)work.size();
+  B.n_dtasks = (int64_t)dtasks.size();
+  double psi_elems = (double)B.n_elem;
+  B.bytes[0] = 8.0 * (op_elems + 2 * psi_elems);
+  B.bytes[1] = 4.0 * (op_elems + 2 * psi_elems);
+  B.bytes[2] = 4.0 * op_elems + 4.0 * 2 * psi_elems;
+  upload(B.d_tiles, tiles, s);
+  upload(B.d_tasks, tasks, s);
+  upload(B.d_work, work, s);
+  upload(B.d_dtiles, dtiles, s);
+  upload(B.d_dtasks, dtasks, s);
+  HCHECK(hipStreamSynchronize(s));
+}
+
+static void validate_ints(const heff_problem* p, Ints& I) {
+  int n = p->n_orb;
+  I.n = n;
+  I.h.assign(p->h, p->h + (size_t)n * n);
+  I.V.assign(p->V, p->V + (size_t)n * n * n * n);
+  double hs = 0, vs = 0;
+  for (double v : I.h) hs = std::max(hs, std::fabs(v));
+  for (double v : I.V) vs = std::max(vs, std::fabs(v));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (std::fabs(I.h[i * n + j] - I.h[j * n + i]) > 1e-12 * std::max(1.0, hs))
+        throw Error(HEFF_EINVAL, "h is not symmetric");
+  auto v = [&](int i, int j, int k, int l) { return I.V[(((size_t)i * n + j) * n + k) * n + l]; };
+  double tol = 1e-12 * std::max(1.0, vs);
+  for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j) for (int k = 0; k < n; ++k) for (int l = 0; l < n; ++l) {
+    double a = v(i, j, k, l);
+    if (std::fabs(a - v(j, i, k, l)) > tol || std::fabs(a - v(i, j, l, k)) > tol || std::fabs(a - v(k, l, i, j)) > tol)
+      throw Error(HEFF_EINVAL, "V lacks the 8-fold (ij|kl) symmetry");
+  }
+}
+
+}  // namespace heff
+
+// ====================================================================== C ABI
+using namespace heff;
+
+#define ABI_BEGIN try {
+#define ABI_END(ctx)                                                \
+  }                                                                 \
+  catch (const Error& e) {                                          \
+    if (ctx) (ctx)->err = e.what();                                 \
+    return e.code;                                                  \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    if (ctx) (ctx)->err = "host allocation failed";                 \
+    return HEFF_ENOMEM;                                             \
+  }                                                                 \
+  catch (const std::exception& e) {                                 \
+    if (ctx) (ctx)->err = e.what();                                 \
+    return HEFF_EINVAL;                                             \
+  }                                                                 \
+  return HEFF_OK;
+
+extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
+  if (!out) return HEFF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HEFF_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return HEFF_EHIP;
+  heff_ctx* c = new (std::nothrow) heff_ctx;
+  if (!c) return HEFF_ENOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  *out = c;
+  return HEFF_OK;
+}
+
+extern "C" int heff_destroy(heff_ctx* c) {
+  delete c;
+  return HEFF_OK;
+}
+
+extern "C" const char* heff_last_error(const heff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t prec_mask, heff_blocks** out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!p || !out || !p->h || !p->V || !p->left || !p->right || !p->iso_left || !p->iso_right)
+    throw Error(HEFF_EINVAL, "null argument");
+  *out = nullptr;
+  const int n = p->n_orb;
+  if (n < 4 || n > 64) throw Error(HEFF_EINVAL, "n_orb must be in [4, 64]");
+  if (p->n_up < 0 || p->n_dn < 0 || p->n_up > n || p->n_dn > n) throw Error(HEFF_EINVAL, "bad electron numbers");
+  if (prec_mask & ~((1u << HEFF_FP32) | (1u << HEFF_BF16X3) | 1u)) throw Error(HEFF_EINVAL, "bad prec_mask");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  auto B = std::make_unique<heff_blocks>();
+  B->ctx = ctx;
+  B->n_orb = n;
+  B->n_up = p->n_up;
+  B->n_dn = p->n_dn;
+  B->k0 = n / 2 - 1;
+  B->prec_mask = prec_mask;
+  const int k0 = B->k0, mR = n - k0 - 2, nmode = 2 * n;
+  Ints I;
+  validate_ints(p, I);
+  std::vector<Bond> lb, rb;
+  for (int l = 0; l <= k0; ++l) lb.push_back(make_bond(p->left[l], "left bond table"));
+  for (int m = 0; m <= mR; ++m) rb.push_back(make_bond(p->right[m], "right bond table"));
+  if (lb[0].n() != 1 || lb[0].nu[0] != 0 || lb[0].nd[0] != 0 || lb[0].dim[0] != 1 ||
+      rb[0].n() != 1 || rb[0].nu[0] != 0 || rb[0].nd[0] != 0 || rb[0].dim[0] != 1)
+    throw Error(HEFF_EINVAL, "empty blocks must have the single sector (0,0) of dimension 1");
+  // left block
+  auto L = initial_block(true, nmode, s);
+  for (int l = 0; l < k0; ++l) {
+    if (!p->iso_left[l]) throw Error(HEFF_EINVAL, "null left isometry");
+    Iso iso;
+    make_iso(iso, lb[l], lb[l + 1], p->iso_left[l], s, "left isometry");
+    L->bond = lb[l];  // (same table; keeps the pointer of the store valid)
+    auto Ln = grow_left(*L, lb[l + 1], iso, l, nmode, I, s);
+    L = std::move(Ln);
+  }
+  auto R = initial_block(false, nmode, s);
+  for (int m = 1; m <= mR; ++m) {
+    if (!p->iso_right[m - 1]) throw Error(HEFF_EINVAL, "null right isometry");
+    Iso iso;
+    make_iso(iso, rb[m - 1], rb[m], p->iso_right[m - 1], s, "right isometry");
+    auto Rn = grow_right(*R, rb[m], iso, n - m, nmode, I, s);
+    R = std::move(Rn);
+  }
+  B->L = std::move(L);
+  B->R = std::move(R);
+  build_psi_layout(*B);
+  build_terms(*B, I);
+  B->Ltmp.run(s);
+  B->Rtmp.run(s);
+  build_tasks(*B, s);
+  // reduced-precision operand copies
+  const double* srcs[4] = {B->L->store.dev.as<double>(), B->Ltmp.tmp.dev.as<double>(),
+                           B->R->store.dev.as<double>(), B->Rtmp.tmp.dev.as<double>()};
+  int64_t sizes[4] = {B->L->store.total, B->Ltmp.tmp.total, B->R->store.total, B->Rtmp.tmp.total};
+  for (int i = 0; i < 4; ++i) {
+    if (prec_mask & (1u << HEFF_FP32)) {
+      B->f32[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * sizeof(float));
+      if (sizes[i]) HCHECK(launch_convert_f32(srcs[i], B->f32[i].as<float>(), sizes[i], s));
+    }
+    if (prec_mask & (1u << HEFF_BF16X3)) {
+      B->bhi[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * 2);
+      B->blo[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * 2);
+      if (sizes[i]) HCHECK(launch_split_bf16(srcs[i], B->bhi[i].as<uint16_t>(), B->blo[i].as<uint16_t>(), sizes[i], s));
+    }
+  }
+  HCHECK(hipStreamSynchronize(s));
+  *out = B.release();
+  ABI_END(ctx)
+}
+
+extern "C" int heff_blocks_free(heff_blocks* b) {
+  if (!b) return HEFF_OK;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
+  return HEFF_OK;
+}
+
+extern "C" int heff_psi_layout(const heff_blocks* b, int64_t* n_elem, int32_t* n_blk, const int32_t** desc,
+                               const int64_t** off) {
+  if (!b) return HEFF_EINVAL;
+  if (n_elem) *n_elem = b->n_elem;
+  if (n_blk) *n_blk = (int32_t)b->blk_off.size();
+  if (desc) *desc = b->blk_desc.data();
+  if (off) *off = b->blk_off.data();
+  return HEFF_OK;
+}
+
+extern "C" int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* flops, double* bytes3) {
+  if (!b) return HEFF_EINVAL;
+  if (n_tasks) *n_tasks = b->n_tasks;
+  if (flops) *flops = b->flops;
+  if (bytes3) for (int i = 0; i < 3; ++i) bytes3[i] = b->bytes[i];
+  return HEFF_OK;
+}
+
+extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out) throw Error(HEFF_EINVAL, "null argument");
+  if (psi == out) throw Error(HEFF_EINVAL, "psi and out alias");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const Tile* tl = b->d_tiles.as<Tile>();
+  const Work* wk = b->d_work.as<Work>();
+  const Task* tk = b->d_tasks.as<Task>();
+  if (prec == HEFF_FP64) {
+    Bases<double> bs{};
+    bs.L[0] = b->L->store.dev.as<double>();
+    bs.L[1] = b->Ltmp.tmp.dev.as<double>();
+    bs.R[0] = b->R->store.dev.as<double>();
+    bs.R[1] = b->Rtmp.tmp.dev.as<double>();
+    bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
+    bs.out = static_cast<double*>(out);
+    HCHECK(launch_chain_f64(tl, wk, b->n_work, tk, bs, s));
+  } else if (prec == HEFF_FP32) {
+    if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
+    Bases<float> bs{};
+    bs.L[0] = b->f32[0].as<float>();
+    bs.L[1] = b->f32[1].as<float>();
+    bs.R[0] = b->f32[2].as<float>();
+    bs.R[1] = b->f32[3].as<float>();
+    bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
+    bs.out = static_cast<float*>(out);
+    HCHECK(launch_chain_f32(tl, wk, b->n_work, tk, bs, s));
+  } else if (prec == HEFF_BF16X3) {
+    if (!(b->prec_mask & (1u << HEFF_BF16X3))) throw Error(HEFF_ENOTSUP, "BF16X3 operands were not built");
+    const uint16_t* Lhi[2] = {b->bhi[0].as<uint16_t>(), b->bhi[1].as<uint16_t>()};
+    const uint16_t* Llo[2] = {b->blo[0].as<uint16_t>(), b->blo[1].as<uint16_t>()};
+    const uint16_t* Rhi[2] = {b->bhi[2].as<uint16_t>(), b->bhi[3].as<uint16_t>()};
+    const uint16_t* Rlo[2] = {b->blo[2].as<uint16_t>(), b->blo[3].as<uint16_t>()};
+    HCHECK(launch_chain_bf16x3(tl, wk, b->n_work, tk, Lhi, Llo, Rhi, Rlo, static_cast<const float*>(psi),
+                               static_cast<float*>(out), s));
+  } else {
+    throw Error(HEFF_EINVAL, "unknown precision");
+  }
+  ABI_END(ctx)
+}
+
+extern "C" int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !diag) throw Error(HEFF_EINVAL, "null argument");
+  HCHECK(hipSetDevice(ctx->device));
+  HCHECK(launch_diag(b->d_dtiles.as<Tile>(), b->n_tiles, b->d_dtasks.as<DiagTask>(),
+                     b->L->store.dev.as<double>(), b->Ltmp.tmp.dev.as<double>(), b->R->store.dev.as<double>(),
+                     b->Rtmp.tmp.dev.as<double>(), diag, ctx->stream));
+  ABI_END(ctx)
+}
+
+// ---------------------------------------------------------------- introspection for tests
+// Copies the blocks of a named renormalized operator to host memory, blocks
+// ordered by in-sector, each row-major.  side 0 = L, 1 = R; kind per the
+// internal Kind enum (H=0, C=1, A=2, B=3, T=4, D=5, DD=6, BB=7, S=8).
+// Returns the number of elements (0 if the operator does not exist).
+extern "C" int64_t heff_debug_op(const heff_blocks* b, int side, int kind, int i, int j, double* host,
+                                 int64_t cap) {
+  if (!b) return -1;
+  const Store& st = side == 0 ? b->L->store : b->R->store;
+  OpId id = st.get({kind, i, j, 0});
+  if (!id.valid()) return 0;
+  const Layout& L = st.lay(id);
+  if (host && cap >= L.size) {
+    (void)hipStreamSynchronize(b->ctx->stream);
+    if (hipMemcpy(host, st.dev.as<double>() + st.offset(id), L.size * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return -2;
+  }
+  return L.size;
+}

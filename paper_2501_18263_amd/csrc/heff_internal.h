@@ -1,0 +1,107 @@
+// Internal structures shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+namespace heff {
+
+// rows of one output block handled by one work item of the product kernels
+constexpr int kRows = 16;
+// largest sector dimension the kernels accept
+constexpr int kMaxDim = 256;
+
+// One block task of the chained product  out += f * op(L) * op(X) * op(R).
+// Shapes: out a x e, op(L) a x b, op(X) b x c, op(R) c x e.  op(M) is M or
+// M^T relative to the row-major storage of M.  In the H_eff product L is a
+// left-block operator block, X a block of Psi and R^T a right-block
+// operator block (Eq. Hamilton_act_U1sym); in the renormalization L = A^T
+// and R = A are isometry blocks and X an old operator block.
+struct Task {
+  double f;
+  int64_t offL, offX, offR;  // element offsets into the selected base arrays
+  uint16_t a, b, c, e;
+  uint32_t flags;
+  uint32_t pad;
+};
+static_assert(sizeof(Task) == 48, "task layout");
+
+enum : uint32_t {
+  T_TL = 1u << 0,    // L stored as b x a
+  T_TX = 1u << 1,    // X stored as c x b
+  T_TR = 1u << 2,    // R stored as e x c
+  T_IDL = 1u << 3,   // op(L) = identity (a == b)
+  T_IDX = 1u << 4,   // op(X) = identity (b == c)
+  T_IDR = 1u << 5,   // op(R) = identity (c == e)
+  T_SELL = 1u << 6,  // L from base 1 (else base 0)
+  T_SELX = 1u << 7,
+  T_SELR = 1u << 8,
+};
+
+// One output block: a x e row-major at offOut, accumulating tasks [t0, t1).
+struct Tile {
+  int64_t offOut;
+  int32_t a, e;
+  int32_t t0, t1;
+};
+static_assert(sizeof(Tile) == 24, "tile layout");
+
+// One work-group's share: rows [row0, row0 + ROWS) of tile `tile`.
+struct Work {
+  int32_t tile;
+  int32_t row0;
+};
+
+// Diagonal task: out[i*e + j] += f * dL[i] * dR[j] with dL the diagonal of
+// an a x a block (stride a+1) and dR of an e x e block; identity -> ones.
+struct DiagTask {
+  double f;
+  int64_t offL, offR;
+  uint32_t flags;  // T_IDL, T_IDR, T_SELL, T_SELR
+  uint32_t pad;
+};
+
+template <typename T>
+struct Bases {
+  const T* L[2];
+  const T* X[2];
+  const T* R[2];
+  T* out;
+};
+
+// ---- launchers (heff_kernels.hip) ----
+hipError_t launch_chain_f64(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
+                            Bases<double> b, hipStream_t s);
+hipError_t launch_chain_f32(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
+                            Bases<float> b, hipStream_t s);
+hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
+                               const uint16_t* Lhi[2], const uint16_t* Llo[2],
+                               const uint16_t* Rhi[2], const uint16_t* Rlo[2],
+                               const float* X, float* out, hipStream_t s);
+hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0,
+                       const double* L1, const double* R0, const double* R1, double* out,
+                       hipStream_t s);
+// C[m x n] = A[m x k] * B[k x n], all row-major, FP64.
+hipError_t launch_gemm_f64(int64_t m, int64_t n, int64_t k, const double* A, const double* B,
+                           double* C, hipStream_t s);
+hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_split_bf16(const double* in, uint16_t* hi, uint16_t* lo, int64_t n,
+                             hipStream_t s);
+hipError_t launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
+
+// ---- Davidson vector kernels ----
+// out[i] = sum_n A[i*lda + n] * x[n], i < k   (FP64, deterministic)
+hipError_t launch_multidot(const double* A, int64_t lda, int k, const double* x, int64_t n,
+                           double* out, double* scratch, hipStream_t s);
+// y[n] = alpha*y[n] + sum_i coef[i] * A[i*lda + n]  (coef on the device)
+hipError_t launch_multiaxpy(const double* A, int64_t lda, int k, const double* coef,
+                            double coef_scale, double* y, double alpha, int64_t n, hipStream_t s);
+}  // namespace heff
+
+// context object behind the opaque heff_ctx handle of the C ABI
+struct heff_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+};

@@ -1,0 +1,241 @@
+"""Python binding of the HIP library ``libheff.so`` (C ABI in include/heff.h).
+
+Argument marshalling only: every arithmetic step of the two-site H_eff
+path runs in the library's HIP kernels.  PyTorch provides device memory and
+the current stream.  Importing this module fails loudly when the built
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libheff.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3"}
+
+# operator kinds of heff_debug_op
+K_H, K_C, K_A, K_B, K_T, K_D, K_DD, K_BB, K_S = range(9)
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libheff.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class _Bond(ctypes.Structure):
+    _fields_ = [("n_sect", ctypes.c_int32), ("nup", ctypes.POINTER(ctypes.c_int32)),
+                ("ndn", ctypes.POINTER(ctypes.c_int32)), ("dim", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("h", ctypes.POINTER(ctypes.c_double)), ("V", ctypes.POINTER(ctypes.c_double)),
+                ("left", ctypes.POINTER(_Bond)), ("right", ctypes.POINTER(_Bond)),
+                ("iso_left", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+                ("iso_right", ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_lib.heff_create.argtypes = [ctypes.POINTER(_vp), _i, _vp]
+_lib.heff_destroy.argtypes = [_vp]
+_lib.heff_last_error.argtypes = [_vp]
+_lib.heff_last_error.restype = ctypes.c_char_p
+_lib.heff_build_blocks.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.c_uint32, ctypes.POINTER(_vp)]
+_lib.heff_blocks_free.argtypes = [_vp]
+_lib.heff_psi_layout.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))]
+_lib.heff_task_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+_lib.heff_apply.argtypes = [_vp, _vp, _i, _vp, _vp]
+_lib.heff_diag.argtypes = [_vp, _vp, _vp]
+_lib.heff_dav_create.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, _vp, ctypes.POINTER(_vp)]
+_lib.heff_davidson_step.argtypes = [_vp, _vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.heff_dav_ritz.argtypes = [_vp, _vp, _vp]
+_lib.heff_dav_free.argtypes = [_vp]
+_lib.heff_debug_op.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
+_lib.heff_debug_op.restype = ctypes.c_int64
+
+EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
+            "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
+            "heff_davidson_step", "heff_dav_ritz", "heff_dav_free")
+
+
+class HeffError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("heff error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Library context on a device, bound to torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = _vp()
+        rc = _lib.heff_create(ctypes.byref(h), device, _vp(stream.cuda_stream))
+        if rc != 0:
+            raise HeffError(rc, "heff_create failed")
+        self._h = h
+
+    def check(self, rc):
+        if rc != 0:
+            raise HeffError(rc, _lib.heff_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.heff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bond_array(tabs, keep):
+    arr = (_Bond * len(tabs))()
+    for i, t in enumerate(tabs):
+        nu = np.array([q[0] for q in t], dtype=np.int32)
+        nd = np.array([q[1] for q in t], dtype=np.int32)
+        dm = np.array(list(t.values()), dtype=np.int32)
+        keep += [nu, nd, dm]
+        arr[i].n_sect = len(t)
+        arr[i].nup = nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[i].ndn = nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[i].dim = dm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return arr
+
+
+class Blocks:
+    """Renormalized operators + task table of one two-site problem."""
+
+    def __init__(self, ctx: Context, problem, precs=(FP64,)):
+        from . import synth
+        self.ctx = ctx
+        keep = []
+        p = problem
+        left = _bond_array(p.left, keep)
+        right = _bond_array(p.right, keep)
+        il = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_left)))()
+        for i in range(len(p.iso_left)):
+            a = np.ascontiguousarray(synth.iso_flat(p.left[i], p.left[i + 1], p.iso_left[i]))
+            keep.append(a)
+            il[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ir = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_right)))()
+        for i in range(len(p.iso_right)):
+            a = np.ascontiguousarray(synth.iso_flat(p.right[i], p.right[i + 1], p.iso_right[i]))
+            keep.append(a)
+            ir[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = np.ascontiguousarray(p.h, dtype=np.float64)
+        V = np.ascontiguousarray(p.V, dtype=np.float64)
+        keep += [h, V]
+        prob = _Problem(p.n_orb, p.n_up, p.n_dn, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), left, right, il, ir)
+        mask = 0
+        for pr in precs:
+            mask |= 1 << pr
+        out = _vp()
+        ctx.check(_lib.heff_build_blocks(ctx._h, ctypes.byref(prob), mask, ctypes.byref(out)))
+        self._h = out
+        self.precs = tuple(precs)
+        n = ctypes.c_int64()
+        nb = ctypes.c_int32()
+        desc = ctypes.POINTER(ctypes.c_int32)()
+        offs = ctypes.POINTER(ctypes.c_int64)()
+        ctx.check(_lib.heff_psi_layout(out, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(desc), ctypes.byref(offs)))
+        self.n_elem = n.value
+        self.blocks = [tuple(desc[6 * i + j] for j in range(6)) + (offs[i],) for i in range(nb.value)]
+
+    def stats(self):
+        nt = ctypes.c_int64()
+        fl = ctypes.c_double()
+        by = (ctypes.c_double * 3)()
+        self.ctx.check(_lib.heff_task_stats(self._h, ctypes.byref(nt), ctypes.byref(fl), by))
+        return dict(n_tasks=nt.value, flops=fl.value, bytes={"fp64": by[0], "fp32": by[1], "bf16x3": by[2]})
+
+    def apply(self, psi, out, prec=FP64):
+        """out = H_eff psi (device tensors: float64 for FP64, float32 otherwise)."""
+        import torch
+        want = torch.float64 if prec == FP64 else torch.float32
+        if psi.dtype != want or out.dtype != want or psi.numel() != self.n_elem or out.numel() != self.n_elem:
+            raise ValueError("psi/out must be %s tensors of %d elements" % (want, self.n_elem))
+        if not (psi.is_cuda and out.is_cuda and psi.is_contiguous() and out.is_contiguous()):
+            raise ValueError("psi/out must be contiguous device tensors")
+        self.ctx.check(_lib.heff_apply(self.ctx._h, self._h, prec, _ptr(psi), _ptr(out)))
+        return out
+
+    def diag(self, out):
+        self.ctx.check(_lib.heff_diag(self.ctx._h, self._h, _ptr(out)))
+        return out
+
+    def debug_op(self, side, kind, i=0, j=0):
+        n = _lib.heff_debug_op(self._h, side, kind, i, j, None, 0)
+        if n <= 0:
+            return None
+        buf = np.empty(n, dtype=np.float64)
+        got = _lib.heff_debug_op(self._h, side, kind, i, j, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+        if got != n:
+            raise HeffError(-4, "debug copy failed")
+        return buf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.heff_blocks_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Davidson:
+    """Device Davidson for the lowest eigenpair of H_eff."""
+
+    def __init__(self, blocks: Blocks, psi0, m_max=24, tol=1e-10):
+        self.blocks = blocks
+        self.tol = tol
+        self.ctx = blocks.ctx
+        h = _vp()
+        self.ctx.check(_lib.heff_dav_create(self.ctx._h, blocks._h, m_max, tol, _ptr(psi0), ctypes.byref(h)))
+        self._h = h
+        self.converged = False
+
+    def step(self, prec=FP64):
+        th = ctypes.c_double()
+        rn = ctypes.c_double()
+        self.ctx.check(_lib.heff_davidson_step(self.ctx._h, self._h, prec, ctypes.byref(th), ctypes.byref(rn)))
+        self.theta, self.resid = th.value, rn.value
+        self.converged = rn.value <= self.tol * abs(th.value)
+        return th.value, rn.value
+
+    def ritz(self, out):
+        self.ctx.check(_lib.heff_dav_ritz(self.ctx._h, self._h, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.heff_dav_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

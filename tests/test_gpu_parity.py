@@ -1,0 +1,169 @@
+"""GPU parity: the HIP library against the CPU oracle (same seeded inputs).
+
+FP64 bar: relative residual ||y_gpu - y_oracle|| / ||y_oracle|| <= 1e-10 and
+elementwise |dy| <= 1e-10 max|y|.  The oracle is O-BLOCK (pinned against the
+explicit P^T H P and full CI in test_oracle_heff.py)."""
+import numpy as np
+import pytest
+
+from paper_2501_18263_amd import synth
+from oracle import block, davidson, fci
+
+from gpu_util import flat_oracle_op, layout_matches
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def heff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_18263_amd import heff as H
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(heff):
+    return heff.Context(0)
+
+
+def _dev(x, dtype=None):
+    return torch.tensor(x, dtype=dtype or torch.float64, device="cuda")
+
+
+def _check_fp64(y, y0, tol=1e-10):
+    assert np.linalg.norm(y - y0) <= tol * np.linalg.norm(y0)
+    assert np.abs(y - y0).max() <= tol * np.abs(y0).max()
+
+
+CASES = [(6, 16, 3), (7, 32, 2), (8, 64, 1), (8, 16, 5), (10, 48, 7), (12, 96, 12)]
+
+
+@pytest.mark.parametrize("N,D,seed", CASES)
+def test_apply_matches_oracle(heff, ctx, N, D, seed):
+    print("case apply N=%d D=%d seed=%d" % (N, D, seed), flush=True)
+    p = synth.make_problem(N, D, seed)
+    B = heff.Blocks(ctx, p)
+    assert layout_matches(p, B.blocks)
+    psi = synth.random_psi(p)
+    terms = block.heff_terms(p)
+    y0 = block.apply(p, terms, psi)
+    out = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.apply(_dev(psi), out)
+    _check_fp64(out.cpu().numpy(), y0)
+    d = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.diag(d)
+    d0 = davidson.diagonal(p, terms)
+    assert np.abs(d.cpu().numpy() - d0).max() <= 1e-10 * np.abs(d0).max()
+
+
+def test_renormalized_operators_match_oracle(heff, ctx):
+    p = synth.make_problem(8, 16, 5)
+    B = heff.Blocks(ctx, p)
+    L = block.build_left(p)
+    R = block.build_right(p)
+    tl, tr = p.tab_L, p.tab_R
+
+    def cmp(side, kind, i, j, op, tab):
+        got = B.debug_op(side, kind, i, j)
+        ref = flat_oracle_op(op, tab)
+        assert got is not None and got.shape == ref.shape, (side, kind, i, j)
+        assert np.abs(got - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (side, kind, i, j)
+
+    cmp(0, heff.K_H, 0, 0, L["H"], tl)
+    for q, op in L["c"].items():
+        cmp(0, heff.K_C, q, 0, op, tl)
+    for (a, b), op in L["A"].items():
+        cmp(0, heff.K_A, a, b, op, tl)
+    for (a, b), op in L["B"].items():
+        cmp(0, heff.K_B, a, b, op, tl)
+    for x, op in L["T"].items():
+        cmp(0, heff.K_T, x, 0, op, tl)
+    cmp(1, heff.K_H, 0, 0, R["H"], tr)
+    for r, op in R["d"].items():
+        cmp(1, heff.K_D, r, 0, op, tr)
+    for (a, b), op in R["DD"].items():
+        cmp(1, heff.K_DD, a, b, op, tr)
+    for (a, b), op in R["BB"].items():
+        cmp(1, heff.K_BB, a, b, op, tr)
+    for x, op in R["S"].items():
+        cmp(1, heff.K_S, x, 0, op, tr)
+
+
+def test_hermitian_and_reproducible(heff, ctx):
+    p = synth.make_problem(16, 256, 21)
+    B = heff.Blocks(ctx, p)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(B.n_elem, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.randn(B.n_elem, dtype=torch.float64, device="cuda", generator=g)
+    hx = torch.empty_like(x)
+    hy = torch.empty_like(y)
+    B.apply(x, hx)
+    B.apply(y, hy)
+    lhs, rhs = float(x @ hy), float(hx @ y)
+    assert abs(lhs - rhs) <= 1e-12 * float(hx.norm() * y.norm())
+    hx2 = torch.empty_like(x)
+    B.apply(x, hx2)
+    assert torch.equal(hx, hx2)          # output-stationary: bitwise reproducible
+
+
+def test_davidson_reaches_fci(heff, ctx):
+    p = synth.make_problem(8, 64, 1)
+    B = heff.Blocks(ctx, p)
+    psi0 = _dev(synth.random_psi(p))
+    dav = heff.Davidson(B, psi0, m_max=24, tol=1e-10)
+    thetas = []
+    for _ in range(400):
+        th, rn = dav.step()
+        thetas.append(th)
+        if dav.converged:
+            break
+    assert dav.converged
+    e_fci = fci.lowest(p.h, p.V, p.n_up, p.n_dn)[0]
+    assert abs(thetas[-1] - e_fci) <= 1e-10 * abs(e_fci)
+    # first iterates against the oracle's Davidson on the same start vector
+    terms = block.heff_terms(p)
+    od = davidson.Davidson(lambda v: block.apply(p, terms, v), davidson.diagonal(p, terms), synth.random_psi(p))
+    for i in range(20):
+        th, _ = od.step()
+        assert abs(th - thetas[i]) <= 1e-9 * abs(th)
+    u = torch.empty_like(psi0)
+    dav.ritz(u)
+    hu = torch.empty_like(u)
+    B.apply(u, hu)
+    assert float((hu - thetas[-1] * u).norm()) <= 1e-8 * abs(thetas[-1])
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 2e-5)])
+def test_mixed_precision_products(heff, ctx, prec, tol):
+    p = synth.make_problem(12, 96, 12)
+    B = heff.Blocks(ctx, p, precs=(0, prec))
+    psi = synth.random_psi(p)
+    y64 = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.apply(_dev(psi), y64)
+    y32 = torch.empty(B.n_elem, dtype=torch.float32, device="cuda")
+    B.apply(_dev(psi, torch.float32), y32, prec=prec)
+    err = float((y32.double() - y64).norm() / y64.norm())
+    print("prec", prec, "rel err", err)
+    assert err <= tol
+
+
+def test_det_isometries_sampled_rows_n24(heff, ctx):
+    # 0/1 isometries: every output entry is a determinant row of H_FCI
+    p = synth.make_problem(24, 1024, 2, iso_kind="det")
+    B = heff.Blocks(ctx, p)
+    psi = synth.random_psi(p)
+    y = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.apply(_dev(psi), y)
+    y = y.cpu().numpy()
+    from oracle import detbasis
+    dets = detbasis.psi_determinants(p)
+    order = np.lexsort((dets[:, 0], dets[:, 1]))
+    basis, xs = dets[order], psi[order]
+    rng = np.random.default_rng(3)
+    idx = rng.choice(len(psi), 64, replace=False)
+    ref = np.array([fci.row_dot(p.h, p.V, dets[i], basis, xs) for i in idx])
+    scale = np.abs(ref).max()
+    assert np.abs(y[idx] - ref).max() <= 1e-10 * scale
