@@ -1,0 +1,154 @@
+"""Benchmark of the two-site DMRG H_eff . psi hot path on one MI355X.
+
+Workload: N = 40 orbitals, 40 electrons, S_z = 0, bond dimension D = 4096,
+middle bond (sites 20, 21 one-based), seeded synthetic Hamiltonian and
+random isometries (see synth.py).  Setup (renormalized operators, task
+table) is untimed.  One step = one Davidson step (one H_eff . psi product
+plus the FP64 subspace update) for each product precision; K timed steps
+follow W warm-up steps.  value = algorithmic TFLOP/s of the product inside
+the FP64 Davidson steps; the FP32 and bf16-split results and their energy
+errors against the FP64 run are reported alongside.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+
+
+def cpu_baseline(n_orb=16, d_max=256, seed=5):
+    """The block-sparse CPU oracle on a bounded sample (N=16, D=256: the
+    same Hamiltonian family, every term, one product); rate in TFLOP/s from
+    the oracle's own flop count."""
+    import numpy as np  # noqa: F401
+
+    from oracle import block
+    from paper_2501_18263_amd import synth
+
+    p = synth.make_problem(n_orb, d_max, seed)
+    terms = block.heff_terms(p)
+    psi = synth.random_psi(p)
+    block.FLOPS[0] = 0.0
+    t0 = time.perf_counter()
+    block.apply(p, terms, psi)
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": block.FLOPS[0] / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "O-BLOCK product, N=%d D=%d (%d-dim psi, %d terms), %.1f s" % (
+                n_orb, d_max, synth.psi_size(p), len(terms), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-orb", type=int, default=40)
+    ap.add_argument("--d", type=int, default=4096)
+    ap.add_argument("--beta", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--precs", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the product shards by terms with one "
+              "all-reduce per product; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2501_18263_amd import heff, synth
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    names = {"fp64": heff.FP64, "fp32": heff.FP32, "bf16x3": heff.BF16X3}
+    precs = [x for x in args.precs.split(",") if x]
+    t0 = time.perf_counter()
+    p = synth.make_problem(args.n_orb, args.d, args.seed, beta=args.beta)
+    psi0 = synth.random_psi(p)
+    log("generated N=%d D=%d psi=%d in %.1fs" % (args.n_orb, args.d, synth.psi_size(p), time.perf_counter() - t0))
+    ctx = heff.Context(0)
+    t0 = time.perf_counter()
+    B = heff.Blocks(ctx, p, precs=tuple(names[x] for x in precs))
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    st = B.stats()
+    vst = B.variant_stats()
+    F = st["flops"]
+    log("build %.1fs  tasks %d  F_alg %.3e  bytes %s" % (t_build, st["n_tasks"], F, st["bytes"]))
+    x0 = torch.tensor(psi0, device="cuda")
+
+    res = {}
+    e_fp64 = None
+    for name in precs:
+        pr = names[name]
+        dav = heff.Davidson(B, x0, m_max=24, tol=1e-10)
+        for _ in range(args.warmup):
+            dav.step(pr)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            th, rn = dav.step(pr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, nl = ctx.timing_read()
+        ctx.timing(False)
+        # energy of the final Ritz vector with an FP64 product (Rayleigh quotient)
+        u = torch.empty_like(x0)
+        dav.ritz(u)
+        hu = torch.empty_like(x0)
+        B.apply(u, hu, heff.FP64)
+        e_corr = float(u @ hu) / float(u @ u)
+        r = {"ms_per_step": 1e3 * dt / args.steps, "tflops": F * args.steps / dt / 1e12,
+             "theta": th, "resid": rn, "energy_fp64_rayleigh": e_corr,
+             "kernel_ms": ms, "kernel_launches": nl}
+        if name == "fp64":
+            e_fp64 = th
+        res[name] = r
+        dav.close()
+        log("%s: %.2f ms/step  %.2f TFLOP/s  theta %.10f  resid %.2e" % (name, r["ms_per_step"], r["tflops"], th, rn))
+    for name in res:
+        if e_fp64 is not None and name != "fp64":
+            res[name]["dE_raw"] = res[name]["theta"] - e_fp64
+            res[name]["dE_fp64_corrected"] = res[name]["energy_fp64_rayleigh"] - res["fp64"]["energy_fp64_rayleigh"]
+
+    head = "fp64" if "fp64" in res else precs[0]
+    hr = res[head]
+    # roofline of the dominant kernel (the variant with the largest time)
+    ms, nl = hr["kernel_ms"], hr["kernel_launches"]
+    v = max(range(len(ms)), key=lambda i: ms[i])
+    avg_s = ms[v] / 1e3 / max(nl[v], 1)
+    achieved = vst[v][0] / avg_s / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
+            "kernel": "chain_mfma variant %d (output blocks with largest dim <= %d)" % (v, [32, 64, 128, 256][v]),
+            "flops_per_launch": vst[v][0], "avg_launch_ms": avg_s * 1e3}
+    out = {
+        "metric": "H_eff·ψ TFLOP/s and Davidson step time, FP64 vs mixed, N=40 D=4096",
+        "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-f32acc"}[head], "data": "synthetic",
+        "config": {"workload": "two-site DMRG H_eff·psi + Davidson, N=%d D=%d" % (args.n_orb, args.d),
+                   "n_orb": args.n_orb, "electrons": p.n_up + p.n_dn, "bond_dim": args.d, "beta": args.beta,
+                   "psi_dim": int(B.n_elem), "tasks": st["n_tasks"], "flops_per_product": F,
+                   "build_s": t_build},
+        "roofline": roof,
+        "by_precision": res,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

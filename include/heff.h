@@ -114,6 +114,19 @@ int heff_psi_layout(const heff_blocks* b, int64_t* n_elem, int32_t* n_blk,
  * block read once + Psi read + Psi' written). bytes may be NULL. */
 int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* flops, double* bytes3);
 
+/* Kernel timing of heff_apply (SURVEY-style per-phase timers): when enabled,
+ * every product launch records HIP events on the context stream around each
+ * of its kernel-variant launches (variants 0..3 handle output blocks whose
+ * largest dimension is <= 32, 64, 128, 256).  heff_timing() enables (1) or
+ * disables (0) recording and clears what was recorded; heff_timing_read()
+ * synchronizes the stream, writes per variant the summed milliseconds
+ * ms[4] and the number of recorded launches launches[4] since the last
+ * clear, then clears.  heff_task_stats_variant() gives the algorithmic
+ * flops per product of variant v and its number of work-groups. */
+int heff_timing(heff_ctx* ctx, int enable);
+int heff_timing_read(heff_ctx* ctx, double* ms, int64_t* launches);
+int heff_task_stats_variant(const heff_blocks* b, int v, double* flops, int64_t* work_items);
+
 /* out = H_eff psi.  psi, out: device arrays of n_elem elements of the
  * precision's storage type (double for FP64, float for FP32 and BF16X3);
  * they must not alias.  Asynchronous on the context stream. */

@@ -612,6 +612,11 @@ def _mid_n(idx):
 # ---------------------------------------------------------------------------
 # the matrix-vector product
 # ---------------------------------------------------------------------------
+# flop counter of the products executed by ``apply`` (instrumentation for the
+# CPU baseline rate: 2 m n k per matrix product)
+FLOPS = [0.0]
+
+
 def apply(p, terms, psi, strict=False):
     """Psi' = H_eff Psi: loop over terms and blocks (the task list of
     Eq. ``Hamilton_act_U1sym``).  ``strict`` raises when a term would move a
@@ -647,6 +652,10 @@ def apply(p, terms, psi, strict=False):
             sgn = (-1) ** ((pm * n_l + pr_ * (n_l + n_mid)) & 1)
             t = x if lm is None else lm @ x
             t = t if rm is None else t @ rm.T
+            if lm is not None:
+                FLOPS[0] += 2.0 * lm.shape[0] * lm.shape[1] * x.shape[1]
+            if rm is not None:
+                FLOPS[0] += 2.0 * t.shape[0] * rm.shape[1] * rm.shape[0]
             for mid2 in np.nonzero(col)[0]:
                 key = (qa2, int(mid2) >> 2, int(mid2) & 3, qb2)
                 if key not in index:

@@ -241,7 +241,8 @@ static unsigned g1d(int64_t n) {
 using namespace heff;
 
 struct heff_dav {
-  heff_ctx* ctx = nullptr;
+  heff_ctx* ctx = nullptr;  // creating context (not used by heff_dav_free)
+  hipStream_t stream = nullptr;
   const heff_blocks* blocks = nullptr;
   int m_max = 24;
   double tol = 1e-10;
@@ -300,6 +301,7 @@ extern "C" int heff_dav_create(heff_ctx* ctx, const heff_blocks* b, int32_t m_ma
   heff_dav* D = new (std::nothrow) heff_dav;
   if (!D) return HEFF_ENOMEM;
   D->ctx = ctx;
+  D->stream = ctx->stream;
   D->blocks = b;
   D->m_max = m_max;
   D->tol = tol;
@@ -430,7 +432,7 @@ extern "C" int heff_dav_ritz(heff_ctx* ctx, heff_dav* D, double* psi) {
 
 extern "C" int heff_dav_free(heff_dav* D) {
   if (!D) return HEFF_OK;
-  (void)hipStreamSynchronize(D->ctx->stream);
+  (void)hipStreamSynchronize(D->stream);
   dav_release(D);
   delete D;
   return HEFF_OK;

@@ -101,8 +101,7 @@ static Bond make_bond(const heff_bond& b, const char* what) {
   if (b.n_sect <= 0 || !b.nup || !b.ndn || !b.dim) throw Error(HEFF_EINVAL, std::string(what) + ": empty table");
   for (int i = 0; i < b.n_sect; ++i) {
     if (b.dim[i] <= 0) throw Error(HEFF_EINVAL, std::string(what) + ": non-positive dimension");
-    if (b.dim[i] > kMaxDim)
-      throw Error(HEFF_EINVAL, std::string(what) + ": sector dimension above " + std::to_string(kMaxDim));
+    if (b.dim[i] > 65535) throw Error(HEFF_EINVAL, std::string(what) + ": sector dimension above 65535");
     if (i > 0 && std::make_pair(b.nup[i - 1], b.ndn[i - 1]) >= std::make_pair(b.nup[i], b.ndn[i]))
       throw Error(HEFF_EINVAL, std::string(what) + ": sectors not strictly sorted");
     r.nu.push_back(b.nup[i]);
@@ -422,20 +421,97 @@ struct LinPlan {
 struct ChainPlan {
   std::vector<Tile> tiles;
   std::vector<Task> tasks;
-  std::vector<Work> work;
-  void add_work_for_tiles(size_t t_begin) {
-    for (size_t t = t_begin; t < tiles.size(); ++t)
-      for (int r = 0; r < tiles[t].a; r += kRows) work.push_back({(int32_t)t, r});
+};
+
+// Split output tiles wider than kMaxDim into column slices and tasks whose
+// inner dimension b exceeds kMaxDim into k ranges (the partial products add
+// up in the output-stationary accumulation), so that every task fits the
+// register budget of the matrix-core kernels.
+static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
+  bool any = false;
+  for (auto& t : tiles) any |= t.e > kMaxDim;
+  for (auto& k : tasks) any |= k.b > kMaxDim;
+  if (!any) return;
+  std::vector<Tile> nt;
+  std::vector<Task> nk;
+  for (const Tile& t : tiles) {
+    for (int n0 = 0; n0 < std::max(t.e, 1); n0 += kMaxDim) {
+      Tile u = t;
+      const int ew = std::min(kMaxDim, t.e - n0);
+      u.offOut = t.offOut + n0;
+      u.e = std::max(ew, 0);
+      u.t0 = (int32_t)nk.size();
+      for (int q = t.t0; q < t.t1; ++q) {
+        Task s = tasks[q];
+        if (n0 > 0) {
+          if (s.flags & T_IDR) throw Error(HEFF_EINVAL, "internal: identity right operand in a split tile");
+          s.offR += (s.flags & T_TR) ? (int64_t)n0 * s.ldR : n0;
+        }
+        s.e = (uint16_t)u.e;
+        const bool direct = (s.flags & (T_IDL | T_IDX)) != 0;
+        if (direct || s.b <= kMaxDim) {
+          nk.push_back(s);
+          continue;
+        }
+        for (int k0 = 0; k0 < s.b; k0 += kMaxDim) {
+          Task r = s;
+          r.b = (uint16_t)std::min(kMaxDim, s.b - k0);
+          r.offL += (s.flags & T_TL) ? (int64_t)k0 * s.ldL : k0;
+          r.offX += (s.flags & T_TX) ? k0 : (int64_t)k0 * s.ldX;
+          nk.push_back(r);
+        }
+      }
+      u.t1 = (int32_t)nk.size();
+      nt.push_back(u);
+    }
+  }
+  tiles.swap(nt);
+  tasks.swap(nk);
+}
+
+// largest dimension a tile's kernel must hold in registers
+static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
+  int d = t.e;
+  for (int k = t.t0; k < t.t1; ++k)
+    if (!(tasks[k].flags & (T_IDL | T_IDX))) d = std::max<int>(d, tasks[k].b);
+  return d;
+}
+
+// Work items of the matrix-core kernels, one list per variant (tiles taken
+// in the given order, each cut into kTileRows-row items).
+static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
+                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants]) {
+  for (int t : order) {
+    int v = variant_of(tile_dim(tiles[t], tasks));
+    for (int r = 0; r < tiles[t].a; r += kTileRows) lists[v].push_back({t, r});
+  }
+}
+
+struct DevWorkSet {
+  DevBuf buf[kNumVariants];
+  WorkSet ws{};
+  void upload_lists(std::vector<Work> (&lists)[kNumVariants], hipStream_t s) {
+    for (int v = 0; v < kNumVariants; ++v) {
+      upload(buf[v], lists[v], s);
+      ws.w[v] = buf[v].as<Work>();
+      ws.n[v] = (int64_t)lists[v].size();
+    }
   }
 };
 
 static void run_chain(ChainPlan& P, Bases<double> b, hipStream_t s) {
-  if (P.work.empty()) return;
-  DevBuf dt, dk, dw;
+  if (P.tiles.empty()) return;
+  split_large(P.tiles, P.tasks);
+  DevBuf dt, dk;
   upload(dt, P.tiles, s);
   upload(dk, P.tasks, s);
-  upload(dw, P.work, s);
-  HCHECK(launch_chain_f64(dt.as<Tile>(), dw.as<Work>(), (int64_t)P.work.size(), dk.as<Task>(), b, s));
+  std::vector<int> order(P.tiles.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::vector<Work> lists[kNumVariants];
+  split_work(P.tiles, P.tasks, order, lists);
+  DevWorkSet dws;
+  dws.upload_lists(lists, s);
+  HCHECK(launch_mfma_f64(dt.as<Tile>(), dws.ws, dk.as<Task>(), b, s));
   HCHECK(hipStreamSynchronize(s));
 }
 
@@ -450,10 +526,11 @@ static void plan_projection(const std::vector<NewDef>& defs, Store& nw, const St
     int64_t obase = nw.offset(d.out);
     for (size_t bi = 0; bi < NL.qin.size(); ++bi) {
       int qo_new = NL.qout[bi], qi_new = NL.qin[bi];
-      Tile tile;
+      Tile tile{};
       tile.offOut = obase + NL.off[bi];
       tile.a = NL.rows[bi];
       tile.e = NL.cols[bi];
+      tile.ldOut = NL.cols[bi];
       tile.t0 = (int32_t)P.tasks.size();
       for (const Src& sr : d.src) {
         const Store* st = sr.x.where == 1 ? tmp : &old;
@@ -494,8 +571,11 @@ static void plan_projection(const std::vector<NewDef>& defs, Store& nw, const St
                 fl |= T_TX;
               }
               t.offX = st->offset(sr.x.id) + XL.off[blk];
+              t.ldX = (uint16_t)XL.cols[blk];
               if (sr.x.where == 1) fl |= T_SELX;
             }
+            t.ldL = (uint16_t)nb.dim[qo_new];
+            t.ldR = (uint16_t)nb.dim[qi_new];
             int sgn = left ? ((opar && ob.par(qb)) ? -1 : 1) : ((xpar && (site_n(si) & 1)) ? -1 : 1);
             t.f = sr.coef * w * sgn;
             t.offL = iso.block(so, qo_new);
@@ -504,7 +584,7 @@ static void plan_projection(const std::vector<NewDef>& defs, Store& nw, const St
             t.b = (uint16_t)ob.dim[qa];
             t.c = (uint16_t)ob.dim[qb];
             t.e = (uint16_t)nb.dim[qi_new];
-            t.flags = fl;
+            t.flags = (uint16_t)fl;
             P.tasks.push_back(t);
           }
         }
@@ -513,7 +593,6 @@ static void plan_projection(const std::vector<NewDef>& defs, Store& nw, const St
       P.tiles.push_back(tile);
     }
   }
-  P.add_work_for_tiles(0);
 }
 
 // ------------------------------------------------------------------ block growth
@@ -814,7 +893,9 @@ struct Term {
 // ====================================================================== public objects
 
 struct heff_blocks {
-  heff_ctx* ctx = nullptr;
+  heff_ctx* ctx = nullptr;  // context that built it (not used after the build)
+  int device = 0;
+  hipStream_t stream = nullptr;
   int n_orb = 0, n_up = 0, n_dn = 0, k0 = 0;
   uint32_t prec_mask = 0;
   std::unique_ptr<heff::Block> L, R;
@@ -828,8 +909,10 @@ struct heff_blocks {
   int64_t n_elem = 0;
   // product task table
   heff::DevBuf d_tiles, d_tasks, d_work, d_dtiles, d_dtasks;
+  heff::DevWorkSet mwork;  // matrix-core work lists
   int64_t n_tiles = 0, n_tasks = 0, n_work = 0, n_dtasks = 0;
   double flops = 0.0, bytes[3] = {0, 0, 0};
+  double vflops[heff::kNumVariants] = {0, 0, 0, 0};  // algorithmic flops per kernel variant
   // reduced-precision operand copies: [L store, L temps, R store, R temps]
   heff::DevBuf f32[4], bhi[4], blo[4];
 };
@@ -1029,6 +1112,10 @@ static double task_flops(const Task& t) {
 static void build_tasks(heff_blocks& B, hipStream_t s) {
   const Bond& bl = B.L->bond;
   const Bond& br = B.R->bond;
+  for (int d : bl.dim)
+    if (d > kMaxDim) throw Error(HEFF_EINVAL, "middle-bond sector dimension above " + std::to_string(kMaxDim));
+  for (int d : br.dim)
+    if (d > kMaxDim) throw Error(HEFF_EINVAL, "middle-bond sector dimension above " + std::to_string(kMaxDim));
   const Store& Ls = B.L->store;
   const Store& Lt = B.Ltmp.tmp;
   const Store& Rs = B.R->store;
@@ -1076,10 +1163,12 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
         t.c = (uint16_t)br.dim[qb];
         t.e = (uint16_t)br.dim[qb2];
         t.offX = B.blk_off[x];
+        t.ldX = (uint16_t)br.dim[qb];
         uint32_t fl = 0;
         if (!lst) fl |= T_IDL;
         else {
           t.offL = lst->offset(tm.l.id) + lst->lay(tm.l.id).off[lblk];
+          t.ldL = (uint16_t)lst->lay(tm.l.id).cols[lblk];
           if (tm.l.trans) fl |= T_TL;
           if (tm.l.where == 1) fl |= T_SELL;
           if (seen.insert({tm.l.where, t.offL}).second) op_elems += (double)t.a * t.b;
@@ -1087,11 +1176,12 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
         if (!rst) fl |= T_IDR;
         else {
           t.offR = rst->offset(tm.r.id) + rst->lay(tm.r.id).off[rblk];
+          t.ldR = (uint16_t)rst->lay(tm.r.id).cols[rblk];
           if (!tm.r.trans) fl |= T_TR;
           if (tm.r.where == 1) fl |= T_SELR;
           if (seen.insert({2 + tm.r.where, t.offR}).second) op_elems += (double)t.c * t.e;
         }
-        t.flags = fl;
+        t.flags = (uint16_t)fl;
         per[y].push_back(t);
         B.flops += task_flops(t);
         if (mid2 == mid && qa2 == qa && qb2 == qb) {
@@ -1110,10 +1200,11 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   std::vector<DiagTask> dtasks;
   std::vector<Work> work;
   for (int y = 0; y < nb; ++y) {
-    Tile t;
+    Tile t{};
     t.offOut = B.blk_off[y];
     t.a = B.blk_desc[6 * y + 4];
     t.e = B.blk_desc[6 * y + 5];
+    t.ldOut = t.e;
     t.t0 = (int32_t)tasks.size();
     tasks.insert(tasks.end(), per[y].begin(), per[y].end());
     t.t1 = (int32_t)tasks.size();
@@ -1134,7 +1225,15 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
     return wa > wb;
   });
   for (int y : order)
-    for (int r = 0; r < tiles[y].a; r += kRows) work.push_back({y, r});
+    for (int r = 0; r < tiles[y].a; r += kPlainRows) work.push_back({y, r});
+  std::vector<Work> lists[kNumVariants];
+  split_work(tiles, tasks, order, lists);
+  B.mwork.upload_lists(lists, s);
+  for (int y = 0; y < nb; ++y) {
+    double fl = 0.0;
+    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
+    B.vflops[variant_of(tile_dim(tiles[y], tasks))] += fl;
+  }
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
   B.n_tiles = nb;
   B.n_tasks = (int64_t)tasks.size();
@@ -1210,6 +1309,13 @@ extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
 }
 
 extern "C" int heff_destroy(heff_ctx* c) {
+  if (c) {
+    (void)hipStreamSynchronize(c->stream);
+    for (int v = 0; v < kNumVariants; ++v) {
+      for (hipEvent_t e : c->ev_start[v]) (void)hipEventDestroy(e);
+      for (hipEvent_t e : c->ev_stop[v]) (void)hipEventDestroy(e);
+    }
+  }
   delete c;
   return HEFF_OK;
 }
@@ -1230,6 +1336,8 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
   hipStream_t s = ctx->stream;
   auto B = std::make_unique<heff_blocks>();
   B->ctx = ctx;
+  B->device = ctx->device;
+  B->stream = ctx->stream;
   B->n_orb = n;
   B->n_up = p->n_up;
   B->n_dn = p->n_dn;
@@ -1291,8 +1399,8 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
 
 extern "C" int heff_blocks_free(heff_blocks* b) {
   if (!b) return HEFF_OK;
-  (void)hipSetDevice(b->ctx->device);
-  (void)hipStreamSynchronize(b->ctx->stream);
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
   delete b;
   return HEFF_OK;
 }
@@ -1325,6 +1433,18 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
   const Tile* tl = b->d_tiles.as<Tile>();
   const Work* wk = b->d_work.as<Work>();
   const Task* tk = b->d_tasks.as<Task>();
+  hipEvent_t evbuf[kNumVariants][2] = {};
+  hipEvent_t(*ev)[2] = nullptr;
+  if (ctx->timing && prec != HEFF_BF16X3) {
+    for (int v = 0; v < kNumVariants; ++v) {
+      if (b->mwork.ws.n[v] <= 0) continue;
+      HCHECK(hipEventCreate(&evbuf[v][0]));
+      HCHECK(hipEventCreate(&evbuf[v][1]));
+      ctx->ev_start[v].push_back(evbuf[v][0]);
+      ctx->ev_stop[v].push_back(evbuf[v][1]);
+    }
+    ev = evbuf;
+  }
   if (prec == HEFF_FP64) {
     Bases<double> bs{};
     bs.L[0] = b->L->store.dev.as<double>();
@@ -1333,7 +1453,7 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     bs.R[1] = b->Rtmp.tmp.dev.as<double>();
     bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
     bs.out = static_cast<double*>(out);
-    HCHECK(launch_chain_f64(tl, wk, b->n_work, tk, bs, s));
+    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, s, ev));
   } else if (prec == HEFF_FP32) {
     if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
     Bases<float> bs{};
@@ -1343,7 +1463,7 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     bs.R[1] = b->f32[3].as<float>();
     bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
     bs.out = static_cast<float*>(out);
-    HCHECK(launch_chain_f32(tl, wk, b->n_work, tk, bs, s));
+    HCHECK(launch_mfma_f32(tl, b->mwork.ws, tk, bs, s, ev));
   } else if (prec == HEFF_BF16X3) {
     if (!(b->prec_mask & (1u << HEFF_BF16X3))) throw Error(HEFF_ENOTSUP, "BF16X3 operands were not built");
     const uint16_t* Lhi[2] = {b->bhi[0].as<uint16_t>(), b->bhi[1].as<uint16_t>()};
@@ -1356,6 +1476,48 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     throw Error(HEFF_EINVAL, "unknown precision");
   }
   ABI_END(ctx)
+}
+
+static void drop_events(heff_ctx* c) {
+  for (int v = 0; v < kNumVariants; ++v) {
+    for (hipEvent_t e : c->ev_start[v]) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_stop[v]) (void)hipEventDestroy(e);
+    c->ev_start[v].clear();
+    c->ev_stop[v].clear();
+  }
+}
+
+extern "C" int heff_timing(heff_ctx* ctx, int enable) {
+  if (!ctx) return HEFF_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_events(ctx);
+  ctx->timing = enable != 0;
+  return HEFF_OK;
+}
+
+extern "C" int heff_timing_read(heff_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  for (int v = 0; v < kNumVariants; ++v) {
+    double tot = 0.0;
+    for (size_t i = 0; i < ctx->ev_start[v].size(); ++i) {
+      float t = 0.f;
+      HCHECK(hipEventElapsedTime(&t, ctx->ev_start[v][i], ctx->ev_stop[v][i]));
+      tot += t;
+    }
+    if (ms) ms[v] = tot;
+    if (launches) launches[v] = (int64_t)ctx->ev_start[v].size();
+  }
+  drop_events(ctx);
+  ABI_END(ctx)
+}
+
+extern "C" int heff_task_stats_variant(const heff_blocks* b, int v, double* flops, int64_t* work_items) {
+  if (!b || v < 0 || v >= kNumVariants) return HEFF_EINVAL;
+  if (flops) *flops = b->vflops[v];
+  if (work_items) *work_items = b->mwork.ws.n[v];
+  return HEFF_OK;
 }
 
 extern "C" int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag) {
@@ -1382,7 +1544,7 @@ extern "C" int64_t heff_debug_op(const heff_blocks* b, int side, int kind, int i
   if (!id.valid()) return 0;
   const Layout& L = st.lay(id);
   if (host && cap >= L.size) {
-    (void)hipStreamSynchronize(b->ctx->stream);
+    (void)hipStreamSynchronize(b->stream);
     if (hipMemcpy(host, st.dev.as<double>() + st.offset(id), L.size * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
       return -2;
   }

@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace heff {
 
-// rows of one output block handled by one work item of the product kernels
-constexpr int kRows = 16;
-// largest sector dimension the kernels accept
+// rows of one output block handled by one work item of the plain kernel
+constexpr int kPlainRows = 16;
+// largest output width and inner dimension one task may have in the
+// matrix-core kernels (larger blocks are split into several tasks / tiles)
 constexpr int kMaxDim = 256;
 
 // One block task of the chained product  out += f * op(L) * op(X) * op(R).
@@ -21,8 +23,8 @@ struct Task {
   double f;
   int64_t offL, offX, offR;  // element offsets into the selected base arrays
   uint16_t a, b, c, e;
-  uint32_t flags;
-  uint32_t pad;
+  uint16_t ldL, ldX, ldR;    // row strides of the stored L, X, R blocks
+  uint16_t flags;
 };
 static_assert(sizeof(Task) == 48, "task layout");
 
@@ -38,13 +40,16 @@ enum : uint32_t {
   T_SELR = 1u << 8,
 };
 
-// One output block: a x e row-major at offOut, accumulating tasks [t0, t1).
+// One output block (or a column slice of one): a x e at offOut with row
+// stride ldOut, accumulating tasks [t0, t1).
 struct Tile {
   int64_t offOut;
   int32_t a, e;
   int32_t t0, t1;
+  int32_t ldOut;
+  int32_t pad;
 };
-static_assert(sizeof(Tile) == 24, "tile layout");
+static_assert(sizeof(Tile) == 32, "tile layout");
 
 // One work-group's share: rows [row0, row0 + ROWS) of tile `tile`.
 struct Work {
@@ -69,11 +74,23 @@ struct Bases {
   T* out;
 };
 
+// Work items of the matrix-core kernels: kTileRows rows of one output block,
+// grouped into kNumVariants lists by the largest dimension D of the block
+// (output columns and every task's inner dimension b): D <= 32, 64, 128, 256.
+constexpr int kTileRows = 64;
+constexpr int kNumVariants = 4;
+inline int variant_of(int d) { return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3; }
+struct WorkSet {
+  const Work* w[kNumVariants];
+  int64_t n[kNumVariants];
+};
+
 // ---- launchers (heff_kernels.hip) ----
-hipError_t launch_chain_f64(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                            Bases<double> b, hipStream_t s);
-hipError_t launch_chain_f32(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                            Bases<float> b, hipStream_t s);
+// ev: optional [kNumVariants][2] start/stop events recorded around each launch
+hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b, hipStream_t s,
+                           hipEvent_t (*ev)[2] = nullptr);
+hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b, hipStream_t s,
+                           hipEvent_t (*ev)[2] = nullptr);
 hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
                                const uint16_t* Lhi[2], const uint16_t* Llo[2],
                                const uint16_t* Rhi[2], const uint16_t* Rlo[2],
@@ -104,4 +121,7 @@ struct heff_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  // per-variant kernel timing of the product (HIP events on `stream`)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start[heff::kNumVariants], ev_stop[heff::kNumVariants];
 };

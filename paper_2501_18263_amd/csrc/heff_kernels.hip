@@ -4,7 +4,7 @@
 // of Eq. Hamilton_act_U1sym (L: left-block operator block, X: Psi block,
 // op(R): transposed right-block operator block) and also the projection
 // A^T (O (x) o) A of the renormalization steps.  Work is output-stationary:
-// one work item owns kRows rows of one output block and accumulates all of
+// one work item owns a row range of one output block and accumulates all of
 // that block's tasks in registers, so no atomics are needed and the sum
 // order is fixed (bitwise reproducible).
 #include "heff_internal.h"
@@ -14,17 +14,10 @@
 namespace heff {
 
 // ------------------------------------------------------------------ helpers
+// elements of op(M) from row-major storage with row stride ld
 template <typename T>
-__device__ __forceinline__ T ld_opL(const T* p, uint32_t fl, int i, int k, int a, int b) {
-  return (fl & T_TL) ? p[(int64_t)k * a + i] : p[(int64_t)i * b + k];
-}
-template <typename T>
-__device__ __forceinline__ T ld_opX(const T* p, uint32_t fl, int k, int j, int b, int c) {
-  return (fl & T_TX) ? p[(int64_t)j * b + k] : p[(int64_t)k * c + j];
-}
-template <typename T>
-__device__ __forceinline__ T ld_opR(const T* p, uint32_t fl, int j, int n, int c, int e) {
-  return (fl & T_TR) ? p[(int64_t)n * c + j] : p[(int64_t)j * e + n];
+__device__ __forceinline__ T ld_op(const T* p, bool trans, int r, int c, int ld) {
+  return trans ? p[(int64_t)c * ld + r] : p[(int64_t)r * ld + c];
 }
 
 // round-to-nearest-even float -> bf16 bits
@@ -37,85 +30,175 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// ------------------------------------------------------------------ chained product (plain)
-// One work-group of 256 threads per work item; T = f * op(L) op(X) rows are
-// staged in LDS, then multiplied by op(R).
 constexpr int kThreads = 256;
-constexpr int kAcc = kRows * kMaxDim / kThreads;
+constexpr int kAcc = kPlainRows * kMaxDim / kThreads;
 
+// ------------------------------------------------------------------ chained product (MFMA)
+// Matrix-core version: one work-group = 4 waves = 64 rows of one output
+// block; wave w owns rows [16w, 16w+16).  Per 16-column chunk of c:
+//   stage 1  T^T = op(X)^T op(L)^T on v_mfma_*_16x16x4, summing over b with
+//            the k order permuted so that lane group g covers the
+//            contiguous range [g*ks, (g+1)*ks): its result leaves register i
+//            of lane (g, n) holding T[row n][c0 + row(i, g)], which is exactly
+//            the A operand of stage 2 for k = c0 + row(i, g) (no LDS round
+//            trip);
+//   stage 2  acc += T op(R) over the same k order, op(R) row c0 + row(i, g).
+// The left operator strip op(L)[row][*] is kept in registers for the whole
+// task (it is reused by every chunk).  KS bounds ks = ceil(b/4), NT bounds
+// the 16-column output tiles.
+// Operand layout of both instructions: lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  Result layout differs: register r of lane l holds
+// D[row(r, l/16)][l%16] with row = 4r + l/16 for f64 and 4(l/16) + r for f32
+// (checked on the device).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void chain_plain(const Tile* __restrict__ tiles,
-                                                        const Work* __restrict__ work,
-                                                        const Task* __restrict__ tasks, Bases<T> B) {
-  __shared__ T Ts[kRows * (kMaxDim + 1)];
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
+};
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
+};
+
+template <typename T, int KS, int NT>
+__global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+                                                  const Task* __restrict__ tasks, Bases<T> B) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
   const Work w = work[blockIdx.x];
   const Tile tile = tiles[w.tile];
-  const int rows = min(kRows, tile.a - w.row0);
+  const int wrow0 = w.row0 + wave * 16;
+  if (wrow0 >= tile.a) return;  // no barriers below: idle waves may leave
+  const int row = wrow0 + n;
+  const bool rowok = row < tile.a;
   const int E = tile.e;
-  const int tid = threadIdx.x;
-  T acc[kAcc];
+  v4 acc[NT];
 #pragma unroll
-  for (int q = 0; q < kAcc; ++q) acc[q] = T(0);
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = v4{0, 0, 0, 0};
   for (int ti = tile.t0; ti < tile.t1; ++ti) {
     const Task t = tasks[ti];
     const uint32_t fl = t.flags;
+    const int b = t.b, c = t.c;
     const T* L = B.L[(fl & T_SELL) ? 1 : 0] + t.offL;
     const T* X = B.X[(fl & T_SELX) ? 1 : 0] + t.offX;
     const T* R = B.R[(fl & T_SELR) ? 1 : 0] + t.offR;
     const T f = (T)t.f;
-    const int b = t.b, c = t.c;
-    // stage 1: Ts[r][j] = f * sum_k op(L)[row0+r][k] op(X)[k][j]
-    for (int idx = tid; idx < rows * c; idx += kThreads) {
-      const int r = idx / c, j = idx - r * c;
-      const int i = w.row0 + r;
-      T v = T(0);
-      if (fl & T_IDL) {
-        v = (fl & T_IDX) ? T(i == j ? 1 : 0) : ld_opX(X, fl, i, j, b, c);
-      } else if (fl & T_IDX) {
-        v = ld_opL(L, fl, i, j, t.a, b);
-      } else {
-        for (int k = 0; k < b; ++k) v += ld_opL(L, fl, i, k, t.a, b) * ld_opX(X, fl, k, j, b, c);
-      }
-      Ts[r * (kMaxDim + 1) + j] = f * v;
-    }
-    __syncthreads();
-    // stage 2: acc[r][n] += sum_j Ts[r][j] op(R)[j][n]
+    const int ks = (b + 3) >> 2;
+    const bool direct = (fl & (T_IDL | T_IDX)) != 0;
+    T Lr[KS];
+    if (!direct) {
 #pragma unroll
-    for (int q = 0; q < kAcc; ++q) {
-      const int idx = tid + q * kThreads;
-      const int r = idx / kMaxDim, n = idx - r * kMaxDim;
-      if (r < rows && n < E) {
-        if (fl & T_IDR) {
-          acc[q] += Ts[r * (kMaxDim + 1) + n];
-        } else {
+      for (int s = 0; s < KS; ++s) {
+        const int k = g * ks + s;
+        T v = T(0);
+        if (s < ks && rowok && k < b) v = ld_op(L, fl & T_TL, row, k, t.ldL);
+        Lr[s] = v;
+      }
+    }
+    for (int c0 = 0; c0 < c; c0 += 16) {
+      v4 Tt = v4{0, 0, 0, 0};
+      if (direct) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = c0 + M::row(i, g);
           T v = T(0);
-          for (int j = 0; j < c; ++j) v += Ts[r * (kMaxDim + 1) + j] * ld_opR(R, fl, j, n, c, E);
-          acc[q] += v;
+          if (rowok && col < c) {
+            if (fl & T_IDL) v = ld_op(X, fl & T_TX, row, col, t.ldX);
+            else v = ld_op(L, fl & T_TL, row, col, t.ldL);
+          }
+          Tt[i] = v;
+        }
+      } else {
+        const int m = c0 + n;
+        const bool mok = m < c;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          if (s < ks) {
+            const int k = g * ks + s;
+            T xa = T(0);
+            if (mok && k < b) xa = ld_op(X, fl & T_TX, k, m, t.ldX);
+            Tt = M::run(xa, Lr[s], Tt);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Tt[i] *= f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int j = c0 + M::row(i, g);
+        const bool jok = j < c;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          if (nt * 16 < E) {
+            const int col = nt * 16 + n;
+            T br = T(0);
+            if (jok && col < E) {
+              if (fl & T_IDR) br = (j == col) ? T(1) : T(0);
+              else br = ld_op(R, fl & T_TR, j, col, t.ldR);
+            }
+            acc[nt] = M::run(Tt[i], br, acc[nt]);
+          }
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kAcc; ++q) {
-    const int idx = tid + q * kThreads;
-    const int r = idx / kMaxDim, n = idx - r * kMaxDim;
-    if (r < rows && n < E) B.out[tile.offOut + (int64_t)(w.row0 + r) * E + n] = acc[q];
+  for (int nt = 0; nt < NT; ++nt) {
+    const int col = nt * 16 + n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wrow0 + M::row(i, g);
+      if (r < tile.a && col < E) B.out[tile.offOut + (int64_t)r * tile.ldOut + col] = acc[nt][i];
+    }
   }
 }
 
-hipError_t launch_chain_f64(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                            Bases<double> b, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chain_plain<double>, dim3((unsigned)n_work), dim3(kThreads), 0, s, tiles, work, tasks, b);
-  return hipGetLastError();
+template <typename T>
+static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<T> b,
+                                       hipStream_t s, hipEvent_t (*ev)[2]) {
+  // largest blocks first: their work items are the longest
+  for (int v = kNumVariants - 1; v >= 0; --v) {
+    if (ws.n[v] <= 0) continue;
+    if (ev && ev[v][0]) {
+      hipError_t e = hipEventRecord(ev[v][0], s);
+      if (e != hipSuccess) return e;
+    }
+    dim3 grid((unsigned)ws.n[v]), blk(256);
+    switch (v) {
+      case 0: hipLaunchKernelGGL((chain_mfma<T, 8, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 1: hipLaunchKernelGGL((chain_mfma<T, 16, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 2: hipLaunchKernelGGL((chain_mfma<T, 32, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      default: hipLaunchKernelGGL((chain_mfma<T, 64, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && ev[v][1]) {
+      e = hipEventRecord(ev[v][1], s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
-hipError_t launch_chain_f32(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                            Bases<float> b, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chain_plain<float>, dim3((unsigned)n_work), dim3(kThreads), 0, s, tiles, work, tasks, b);
-  return hipGetLastError();
+hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b, hipStream_t s,
+                           hipEvent_t (*ev)[2]) {
+  return launch_mfma_variants<double>(tiles, ws, tasks, b, s, ev);
+}
+hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b, hipStream_t s,
+                           hipEvent_t (*ev)[2]) {
+  return launch_mfma_variants<float>(tiles, ws, tasks, b, s, ev);
 }
 
 // ------------------------------------------------------------------ chained product, bf16 split
@@ -136,10 +219,10 @@ __device__ __forceinline__ float mul3(float ah, float al, float bh, float bl) { 
 __global__ __launch_bounds__(kThreads) void chain_bf16x3_plain(const Tile* __restrict__ tiles,
                                                                const Work* __restrict__ work,
                                                                const Task* __restrict__ tasks, Bf16Args B) {
-  __shared__ float Ts[kRows * (kMaxDim + 1)];
+  __shared__ float Ts[kPlainRows * (kMaxDim + 1)];
   const Work w = work[blockIdx.x];
   const Tile tile = tiles[w.tile];
-  const int rows = min(kRows, tile.a - w.row0);
+  const int rows = min(kPlainRows, tile.a - w.row0);
   const int E = tile.e;
   const int tid = threadIdx.x;
   float acc[kAcc];
@@ -161,13 +244,13 @@ __global__ __launch_bounds__(kThreads) void chain_bf16x3_plain(const Tile* __res
       const int i = w.row0 + r;
       float v = 0.f;
       if (fl & T_IDL) {
-        v = ld_opX(X, fl, i, j, b, c);
+        v = ld_op(X, fl & T_TX, i, j, t.ldX);
       } else {
         for (int k = 0; k < b; ++k) {
-          float x = ld_opX(X, fl, k, j, b, c);
+          float x = ld_op(X, fl & T_TX, k, j, t.ldX);
           uint16_t xh = f2bf(x);
           uint16_t xl = f2bf(x - bf2f(xh));
-          v += mul3(bf2f(ld_opL(Lh, fl, i, k, t.a, b)), bf2f(ld_opL(Ll, fl, i, k, t.a, b)), bf2f(xh), bf2f(xl));
+          v += mul3(bf2f(ld_op(Lh, fl & T_TL, i, k, t.ldL)), bf2f(ld_op(Ll, fl & T_TL, i, k, t.ldL)), bf2f(xh), bf2f(xl));
         }
       }
       Ts[r * (kMaxDim + 1) + j] = f * v;
@@ -186,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void chain_bf16x3_plain(const Tile* __res
             float tv = Ts[r * (kMaxDim + 1) + j];
             uint16_t th = f2bf(tv);
             uint16_t tl = f2bf(tv - bf2f(th));
-            v += mul3(bf2f(th), bf2f(tl), bf2f(ld_opR(Rh, fl, j, n, c, E)), bf2f(ld_opR(Rl, fl, j, n, c, E)));
+            v += mul3(bf2f(th), bf2f(tl), bf2f(ld_op(Rh, fl & T_TR, j, n, t.ldR)), bf2f(ld_op(Rl, fl & T_TR, j, n, t.ldR)));
           }
           acc[q] += v;
         }
@@ -198,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void chain_bf16x3_plain(const Tile* __res
   for (int q = 0; q < kAcc; ++q) {
     const int idx = tid + q * kThreads;
     const int r = idx / kMaxDim, n = idx - r * kMaxDim;
-    if (r < rows && n < E) B.out[tile.offOut + (int64_t)(w.row0 + r) * E + n] = acc[q];
+    if (r < rows && n < E) B.out[tile.offOut + (int64_t)(w.row0 + r) * tile.ldOut + n] = acc[q];
   }
 }
 

@@ -9,6 +9,9 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
+
+_finalizing = sys.is_finalizing
 
 import numpy as np
 
@@ -58,12 +61,17 @@ _lib.heff_dav_create.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_double, _vp,
 _lib.heff_davidson_step.argtypes = [_vp, _vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.heff_dav_ritz.argtypes = [_vp, _vp, _vp]
 _lib.heff_dav_free.argtypes = [_vp]
+_lib.heff_timing.argtypes = [_vp, _i]
+_lib.heff_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_task_stats_variant.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_debug_op.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
 _lib.heff_debug_op.restype = ctypes.c_int64
 
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
-            "heff_davidson_step", "heff_dav_ritz", "heff_dav_free")
+            "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
+            "heff_task_stats_variant")
+N_VARIANTS = 4
 
 
 class HeffError(RuntimeError):
@@ -95,12 +103,25 @@ class Context:
         if rc != 0:
             raise HeffError(rc, _lib.heff_last_error(self._h).decode())
 
+    def timing(self, enable=True):
+        """Enable/disable per-variant HIP-event timing of products (clears)."""
+        self.check(_lib.heff_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        """(ms[4], launches[4]) summed since the last clear; clears."""
+        ms = (ctypes.c_double * N_VARIANTS)()
+        n = (ctypes.c_int64 * N_VARIANTS)()
+        self.check(_lib.heff_timing_read(self._h, ms, n))
+        return list(ms), list(n)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.heff_destroy(self._h)
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:
@@ -168,6 +189,16 @@ class Blocks:
         self.ctx.check(_lib.heff_task_stats(self._h, ctypes.byref(nt), ctypes.byref(fl), by))
         return dict(n_tasks=nt.value, flops=fl.value, bytes={"fp64": by[0], "fp32": by[1], "bf16x3": by[2]})
 
+    def variant_stats(self):
+        """[(algorithmic flops per product, work-groups)] per kernel variant."""
+        out = []
+        for v in range(N_VARIANTS):
+            fl = ctypes.c_double()
+            nw = ctypes.c_int64()
+            self.ctx.check(_lib.heff_task_stats_variant(self._h, v, ctypes.byref(fl), ctypes.byref(nw)))
+            out.append((fl.value, nw.value))
+        return out
+
     def apply(self, psi, out, prec=FP64):
         """out = H_eff psi (device tensors: float64 for FP64, float32 otherwise)."""
         import torch
@@ -199,6 +230,8 @@ class Blocks:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:
@@ -235,6 +268,8 @@ class Davidson:
             self._h = None
 
     def __del__(self):
+        if _finalizing():  # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:

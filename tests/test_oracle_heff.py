@@ -106,3 +106,21 @@ def test_davidson_reaches_fci(exact8):
     assert abs(dav.theta - e_fci) <= 1e-10 * abs(e_fci)
     V = np.stack(dav.V, 1)
     assert np.abs(V.T @ V - np.eye(V.shape[1])).max() < 1e-12
+
+
+def test_davidson_transient_is_rounding_sensitive(exact8):
+    # Documents why GPU/oracle Davidson iterates are compared only for the
+    # first steps: perturbing every product by 1e-16 (relative, random)
+    # changes the Ritz value by far more than rounding after a few steps,
+    # while both runs still converge to the same eigenvalue.
+    p, H = exact8
+    terms = block.heff_terms(p)
+    d = davidson.diagonal(p, terms)
+    psi = synth.random_psi(p)
+    rng = np.random.default_rng(0)
+    a = davidson.Davidson(lambda v: H @ v, d, psi)
+    b = davidson.Davidson(lambda v: (H @ v) * (1 + 1e-16 * rng.standard_normal(len(v))), d, psi)
+    diffs = []
+    for _ in range(12):
+        diffs.append(abs(a.step()[0] - b.step()[0]))
+    assert max(diffs[:3]) < 1e-12 and max(diffs) > 1e-8
