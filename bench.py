@@ -91,6 +91,22 @@ def main():
     e_fp64 = None
     for name in precs:
         pr = names[name]
+        # product alone: events on the product's stream around each call
+        dt_ = torch.float64 if pr == heff.FP64 else torch.float32
+        xs = x0.to(dt_)
+        ys = torch.empty_like(xs)
+        B.apply(xs, ys, pr)
+        torch.cuda.synchronize()
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        for i in range(args.steps):
+            ev0[i].record()
+            B.apply(xs, ys, pr)
+            ev1[i].record()
+        torch.cuda.synchronize()
+        prod_ms = sorted(a.elapsed_time(b) for a, b in zip(ev0, ev1))
+        prod_med = prod_ms[len(prod_ms) // 2]
+        log("%s product: median %.3f ms  %.2f TFLOP/s" % (name, prod_med, F / prod_med / 1e9))
         dav = heff.Davidson(B, x0, m_max=24, tol=1e-10)
         for _ in range(args.warmup):
             dav.step(pr)
@@ -110,6 +126,7 @@ def main():
         B.apply(u, hu, heff.FP64)
         e_corr = float(u @ hu) / float(u @ u)
         r = {"ms_per_step": 1e3 * dt / args.steps, "tflops": F * args.steps / dt / 1e12,
+             "product_ms_median": prod_med, "product_tflops": F / prod_med / 1e9,
              "theta": th, "resid": rn, "energy_fp64_rayleigh": e_corr,
              "kernel_ms": ms, "kernel_launches": nl}
         if name == "fp64":

@@ -135,6 +135,47 @@ int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, v
 /* diag[i] = H_eff[i,i] (device, n_elem doubles).  Asynchronous. */
 int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag);
 
+/* Truncation (the SVD step after Diag_H; Sec. II.A keeps the D largest
+ * singular values).  Psi (device, n_elem doubles) is reshaped per sector Q'
+ * of the enlarged left block L + {k} into M[(s_k, alpha), (s_k+1, beta)];
+ * the squared singular values and left singular vectors are taken as the
+ * eigenpairs of M M^T (FP64 Jacobi on the device); the d_keep largest over
+ * all sectors are kept (ties: sector order, then rank).  The result object
+ * holds the kept singular values (descending), the discarded weight (sum of
+ * the other squared singular values), the new bond table of the block
+ * L + {k} and the new left isometry of site k on the device in the layout of
+ * heff_problem (rows stacked by s_k then alpha, columns of each sector in
+ * descending order, each signed so its largest-magnitude entry is
+ * positive).  Synchronizes the stream. */
+typedef struct heff_trunc heff_trunc;
+int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* psi, int32_t d_keep, heff_trunc** out);
+int heff_trunc_info(const heff_trunc* t, int32_t* n_kept, double* discarded, int32_t* n_sect, int64_t* iso_len);
+/* sing[n_kept], nup/ndn/dim[n_sect] are caller-owned host arrays; iso_dev is
+ * a caller-owned device array of iso_len doubles receiving the isometry
+ * (each may be NULL).  Synchronizes the stream. */
+int heff_trunc_get(heff_ctx* ctx, const heff_trunc* t, double* sing, int32_t* nup, int32_t* ndn, int32_t* dim,
+                   double* iso_dev);
+int heff_trunc_free(heff_trunc* t);
+
+/* Batches: n independent problems (each built with FP32 operands) in one
+ * persistent launch per kernel variant, captured once into a HIP graph on
+ * an internal stream and replayed (ordered after / before the context
+ * stream by events).  x_dev / y_dev are caller-owned concatenated FP32 device
+ * vectors (input, output; no alias) of n_total elements where problem i
+ * occupies [offsets[i], offsets[i] + n_elem_i) (heff_batch_layout); they and
+ * the problems must outlive the batch.  heff_batch_set_grid() sets the
+ * persistent work-groups per variant (the autotuner's knob) and drops the
+ * captured graph. */
+typedef struct heff_batch heff_batch;
+int heff_batch_layout(const heff_blocks* const* probs, int32_t n, int64_t* offsets, int64_t* n_total);
+int heff_batch_create(heff_ctx* ctx, const heff_blocks* const* probs, int32_t n, float* x_dev, float* y_dev,
+                      heff_batch** out);
+int heff_batch_io(const heff_batch* b, const int64_t** offsets, int64_t* n_total);
+int heff_batch_set_grid(heff_batch* b, const int32_t* grid /* [4] */);
+int heff_batch_stats(const heff_batch* b, double* flops, int32_t* grid /* [4] */, int64_t* work_items /* [4] */);
+int heff_batch_apply(heff_ctx* ctx, heff_batch* b, int use_graph);
+int heff_batch_free(heff_batch* b);
+
 /* Davidson eigensolver for the lowest eigenpair of H_eff (the Diag_H step).
  * m_max in [3, 29] basis vectors, restart to {Ritz vector, previous Ritz
  * vector}; converged when ||r|| <= tol*|theta|.  psi0: device, n_elem

@@ -910,6 +910,8 @@ struct heff_blocks {
   // product task table
   heff::DevBuf d_tiles, d_tasks, d_work, d_dtiles, d_dtasks;
   heff::DevWorkSet mwork;  // matrix-core work lists
+  std::vector<heff::Tile> h_tiles;  // host copies (used to assemble batches)
+  std::vector<heff::Task> h_tasks;
   int64_t n_tiles = 0, n_tasks = 0, n_work = 0, n_dtasks = 0;
   double flops = 0.0, bytes[3] = {0, 0, 0};
   double vflops[heff::kNumVariants] = {0, 0, 0, 0};  // algorithmic flops per kernel variant
@@ -1245,6 +1247,8 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   B.bytes[2] = 4.0 * op_elems + 4.0 * 2 * psi_elems;
   upload(B.d_tiles, tiles, s);
   upload(B.d_tasks, tasks, s);
+  B.h_tiles = tiles;
+  B.h_tasks = tasks;
   upload(B.d_work, work, s);
   upload(B.d_dtiles, dtiles, s);
   upload(B.d_dtasks, dtasks, s);
@@ -1435,7 +1439,7 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
   const Task* tk = b->d_tasks.as<Task>();
   hipEvent_t evbuf[kNumVariants][2] = {};
   hipEvent_t(*ev)[2] = nullptr;
-  if (ctx->timing && prec != HEFF_BF16X3) {
+  if (ctx->timing) {
     for (int v = 0; v < kNumVariants; ++v) {
       if (b->mwork.ws.n[v] <= 0) continue;
       HCHECK(hipEventCreate(&evbuf[v][0]));
@@ -1470,8 +1474,8 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     const uint16_t* Llo[2] = {b->blo[0].as<uint16_t>(), b->blo[1].as<uint16_t>()};
     const uint16_t* Rhi[2] = {b->bhi[2].as<uint16_t>(), b->bhi[3].as<uint16_t>()};
     const uint16_t* Rlo[2] = {b->blo[2].as<uint16_t>(), b->blo[3].as<uint16_t>()};
-    HCHECK(launch_chain_bf16x3(tl, wk, b->n_work, tk, Lhi, Llo, Rhi, Rlo, static_cast<const float*>(psi),
-                               static_cast<float*>(out), s));
+    HCHECK(launch_bf16x3_mfma(tl, b->mwork.ws, tk, Lhi, Llo, Rhi, Rlo, static_cast<const float*>(psi),
+                              static_cast<float*>(out), s, ev));
   } else {
     throw Error(HEFF_EINVAL, "unknown precision");
   }
@@ -1529,6 +1533,382 @@ extern "C" int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag) {
                      b->L->store.dev.as<double>(), b->Ltmp.tmp.dev.as<double>(), b->R->store.dev.as<double>(),
                      b->Rtmp.tmp.dev.as<double>(), diag, ctx->stream));
   ABI_END(ctx)
+}
+
+// ---------------------------------------------------------------- batches of problems
+// Many independent two-site problems in one persistent launch per kernel
+// variant: the task tables are concatenated (Psi and output offsets shifted
+// into one concatenated FP32 vector each, tile.prob selects the problem's
+// operator stores), and the launch sequence is captured once in a HIP graph
+// on an internal stream and replayed by every heff_batch_apply.
+struct heff_batch {
+  int device = 0;
+  int n = 0;
+  std::vector<int64_t> off;
+  int64_t n_total = 0;
+  double flops = 0.0;
+  float* x = nullptr;  // caller-owned concatenated input / output
+  float* y = nullptr;
+  heff::DevBuf tiles, tasks, pb;
+  heff::DevWorkSet work;
+  int grid[heff::kNumVariants] = {0, 0, 0, 0};
+  hipStream_t gs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~heff_batch() {
+    if (gs) (void)hipStreamSynchronize(gs);
+    drop_graph();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (gs) (void)hipStreamDestroy(gs);
+  }
+};
+
+extern "C" int heff_batch_create(heff_ctx* ctx, const heff_blocks* const* probs, int32_t n, float* x_dev,
+                                 float* y_dev, heff_batch** out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!probs || !out || n <= 0 || !x_dev || !y_dev || x_dev == y_dev) throw Error(HEFF_EINVAL, "bad argument");
+  *out = nullptr;
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  auto Bt = std::make_unique<heff_batch>();
+  Bt->device = ctx->device;
+  Bt->n = n;
+  std::vector<Tile> tiles;
+  std::vector<Task> tasks;
+  std::vector<ProbBases<float>> pb(n);
+  for (int i = 0; i < n; ++i) {
+    const heff_blocks* b = probs[i];
+    if (!b) throw Error(HEFF_EINVAL, "null problem");
+    if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "batched problems need FP32 operands");
+    Bt->off.push_back(Bt->n_total);
+    const int64_t xo = Bt->n_total;
+    const int32_t tb = (int32_t)tasks.size();
+    for (Tile t : b->h_tiles) {
+      t.offOut += xo;
+      t.t0 += tb;
+      t.t1 += tb;
+      t.prob = i;
+      tiles.push_back(t);
+    }
+    for (Task k : b->h_tasks) {
+      k.offX += xo;
+      tasks.push_back(k);
+    }
+    pb[i].L[0] = b->f32[0].as<float>();
+    pb[i].L[1] = b->f32[1].as<float>();
+    pb[i].R[0] = b->f32[2].as<float>();
+    pb[i].R[1] = b->f32[3].as<float>();
+    Bt->n_total += b->n_elem;
+    Bt->flops += b->flops;
+  }
+  if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "batch task table too large");
+  std::vector<double> cost(tiles.size(), 0.0);
+  for (size_t t = 0; t < tiles.size(); ++t)
+    for (int k = tiles[t].t0; k < tiles[t].t1; ++k) cost[t] += task_flops(tasks[k]) / std::max(1, tiles[t].a);
+  std::vector<int> order(tiles.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<Work> lists[kNumVariants];
+  split_work(tiles, tasks, order, lists);
+  Bt->work.upload_lists(lists, s);
+  upload(Bt->tiles, tiles, s);
+  upload(Bt->tasks, tasks, s);
+  upload(Bt->pb, pb, s);
+  Bt->x = x_dev;
+  Bt->y = y_dev;
+  for (int v = 0; v < kNumVariants; ++v) Bt->grid[v] = (int)std::min<int64_t>(Bt->work.ws.n[v], 512);
+  HCHECK(hipStreamCreateWithFlags(&Bt->gs, hipStreamNonBlocking));
+  HCHECK(hipEventCreateWithFlags(&Bt->ev_in, hipEventDisableTiming));
+  HCHECK(hipEventCreateWithFlags(&Bt->ev_out, hipEventDisableTiming));
+  HCHECK(hipStreamSynchronize(s));
+  *out = Bt.release();
+  ABI_END(ctx)
+}
+
+extern "C" int heff_batch_layout(const heff_blocks* const* probs, int32_t n, int64_t* offsets, int64_t* n_total) {
+  if (!probs || n <= 0) return HEFF_EINVAL;
+  int64_t o = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!probs[i]) return HEFF_EINVAL;
+    if (offsets) offsets[i] = o;
+    o += probs[i]->n_elem;
+  }
+  if (n_total) *n_total = o;
+  return HEFF_OK;
+}
+
+extern "C" int heff_batch_io(const heff_batch* b, const int64_t** offsets, int64_t* n_total) {
+  if (!b) return HEFF_EINVAL;
+  if (offsets) *offsets = b->off.data();
+  if (n_total) *n_total = b->n_total;
+  return HEFF_OK;
+}
+
+extern "C" int heff_batch_set_grid(heff_batch* b, const int32_t* grid) {
+  if (!b || !grid) return HEFF_EINVAL;
+  for (int v = 0; v < kNumVariants; ++v) {
+    if (grid[v] <= 0) return HEFF_EINVAL;
+    b->grid[v] = (int)std::min<int64_t>(grid[v], std::max<int64_t>(b->work.ws.n[v], 1));
+  }
+  (void)hipStreamSynchronize(b->gs);
+  b->drop_graph();
+  return HEFF_OK;
+}
+
+extern "C" int heff_batch_stats(const heff_batch* b, double* flops, int32_t* grid, int64_t* work_items) {
+  if (!b) return HEFF_EINVAL;
+  if (flops) *flops = b->flops;
+  for (int v = 0; v < kNumVariants; ++v) {
+    if (grid) grid[v] = b->grid[v];
+    if (work_items) work_items[v] = b->work.ws.n[v];
+  }
+  return HEFF_OK;
+}
+
+// y = H_eff x for every problem (FP32).  use_graph: 1 = capture on first use
+// and replay, 0 = plain launches on the context stream.
+extern "C" int heff_batch_apply(heff_ctx* ctx, heff_batch* b, int use_graph) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b) throw Error(HEFF_EINVAL, "null batch");
+  HCHECK(hipSetDevice(ctx->device));
+  const Tile* tl = b->tiles.as<Tile>();
+  const Task* tk = b->tasks.as<Task>();
+  const ProbBases<float>* pb = b->pb.as<ProbBases<float>>();
+  if (!use_graph) {
+    HCHECK(launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, ctx->stream));
+  } else {
+    if (!b->exec) {
+      HCHECK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
+      hipError_t e = launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, b->gs);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(b->gs, &g);
+      HCHECK(e);
+      HCHECK(e2);
+      b->graph = g;
+      HCHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    HCHECK(hipEventRecord(b->ev_in, ctx->stream));
+    HCHECK(hipStreamWaitEvent(b->gs, b->ev_in, 0));
+    HCHECK(hipGraphLaunch(b->exec, b->gs));
+    HCHECK(hipEventRecord(b->ev_out, b->gs));
+    HCHECK(hipStreamWaitEvent(ctx->stream, b->ev_out, 0));
+  }
+  ABI_END(ctx)
+}
+
+extern "C" int heff_batch_free(heff_batch* b) {
+  if (b) (void)hipSetDevice(b->device);
+  delete b;
+  return HEFF_OK;
+}
+
+// ---------------------------------------------------------------- truncation (SVD step)
+// The two-site vector is reshaped, per sector Q' of the enlarged left block
+// L + {k}, into M_Q'[(s_k, alpha), (s_k+1, beta)]; its left singular vectors
+// and squared singular values are the eigenpairs of rho_Q' = M M^T (the
+// reduced density matrix of L + {k}).  rho is assembled from Psi blocks by
+// the chained-product kernel, diagonalized by Jacobi in FP64, and the D
+// largest singular values over all sectors are kept (Sec. II.A).
+struct heff_trunc {
+  int32_t n_kept = 0;
+  double discarded = 0.0;
+  std::vector<double> sing;
+  std::vector<int32_t> nup, ndn, dim;
+  heff::DevBuf iso;
+  int64_t iso_len = 0;
+};
+
+extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* psi, int32_t d_keep, heff_trunc** out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out || d_keep <= 0) throw Error(HEFF_EINVAL, "bad argument");
+  *out = nullptr;
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const Bond& bl = b->L->bond;
+  // enlarged sectors and their row blocks (s_k, q_alpha)
+  std::map<std::pair<int, int>, int> qidx;
+  std::vector<std::pair<int, int>> qlist;
+  for (int qa = 0; qa < bl.n(); ++qa)
+    for (int sk = 0; sk < 4; ++sk) qidx[{bl.nu[qa] + SQU[sk], bl.nd[qa] + SQD[sk]}] = 0;
+  for (auto& kv : qidx) { kv.second = (int)qlist.size(); qlist.push_back(kv.first); }
+  const int nq = (int)qlist.size();
+  std::vector<std::array<int, 4>> roff(nq), rq(nq);  // per sector, per s: row offset / q_alpha index
+  std::vector<int> nrow(nq, 0);
+  for (int q = 0; q < nq; ++q)
+    for (int sk = 0; sk < 4; ++sk) {
+      int qa = bl.find(qlist[q].first - SQU[sk], qlist[q].second - SQD[sk]);
+      rq[q][sk] = qa;
+      roff[q][sk] = nrow[q];
+      if (qa >= 0) nrow[q] += bl.dim[qa];
+    }
+  std::vector<int64_t> moff(nq);
+  int64_t mtot = 0;
+  for (int q = 0; q < nq; ++q) {
+    if (nrow[q] > kMaxEig) throw Error(HEFF_EINVAL, "enlarged sector larger than the eigensolver limit");
+    moff[q] = mtot;
+    mtot += (int64_t)nrow[q] * nrow[q];
+  }
+  // rho_Q'[(s,a),(s',a')] = sum_{s1} Psi(a, s, s1) Psi(a', s', s1)^T
+  ChainPlan P;
+  for (int q = 0; q < nq; ++q)
+    for (int si = 0; si < 4; ++si) {
+      int qa = rq[q][si];
+      if (qa < 0) continue;
+      for (int sj = 0; sj < 4; ++sj) {
+        int qa2 = rq[q][sj];
+        if (qa2 < 0) continue;
+        Tile t{};
+        t.offOut = moff[q] + (int64_t)roff[q][si] * nrow[q] + roff[q][sj];
+        t.a = bl.dim[qa];
+        t.e = bl.dim[qa2];
+        t.ldOut = nrow[q];
+        t.t0 = (int32_t)P.tasks.size();
+        for (int s1 = 0; s1 < 4; ++s1) {
+          auto ix = b->blk_index.find({qa, si, s1});
+          auto iy = b->blk_index.find({qa2, sj, s1});
+          if (ix == b->blk_index.end() || iy == b->blk_index.end()) continue;
+          const int x = ix->second, y = iy->second;
+          const int c = b->blk_desc[6 * x + 5];
+          Task k{};
+          k.f = 1.0;
+          k.offL = b->blk_off[x];
+          k.offR = b->blk_off[y];
+          k.a = (uint16_t)bl.dim[qa];
+          k.b = k.c = (uint16_t)c;
+          k.e = (uint16_t)bl.dim[qa2];
+          k.ldL = (uint16_t)c;
+          k.ldR = (uint16_t)c;
+          k.flags = (uint16_t)(T_IDX | T_TR);
+          P.tasks.push_back(k);
+        }
+        t.t1 = (int32_t)P.tasks.size();
+        P.tiles.push_back(t);
+      }
+    }
+  DevBuf rho, vec;
+  rho.alloc((size_t)std::max<int64_t>(mtot, 1) * sizeof(double));
+  vec.alloc((size_t)std::max<int64_t>(mtot, 1) * sizeof(double));
+  Bases<double> bs{};
+  bs.L[0] = bs.L[1] = psi;
+  bs.R[0] = bs.R[1] = psi;
+  bs.X[0] = bs.X[1] = psi;
+  bs.out = rho.as<double>();
+  run_chain(P, bs, s);
+  std::vector<EigJob> jobs;
+  std::vector<int> job_q;
+  for (int q = 0; q < nq; ++q)
+    if (nrow[q] > 0) { jobs.push_back({moff[q], nrow[q], 0}); job_q.push_back(q); }
+  DevBuf djobs;
+  upload(djobs, jobs, s);
+  HCHECK(launch_sym_jacobi(djobs.as<EigJob>(), (int)jobs.size(), rho.as<double>(), vec.as<double>(), s));
+  // eigenvalues = diagonals
+  std::vector<std::vector<double>> lam(nq);
+  for (int q = 0; q < nq; ++q) {
+    lam[q].resize(nrow[q]);
+    if (nrow[q] == 0) continue;
+    HCHECK(hipMemcpy2DAsync(lam[q].data(), sizeof(double), rho.as<double>() + moff[q], (size_t)(nrow[q] + 1) * sizeof(double),
+                            sizeof(double), nrow[q], hipMemcpyDeviceToHost, s));
+  }
+  HCHECK(hipStreamSynchronize(s));
+  // descending order inside each sector, then the global selection
+  std::vector<std::vector<int>> ord(nq);
+  struct Cand { double lam; int q, rank; };
+  std::vector<Cand> all;
+  for (int q = 0; q < nq; ++q) {
+    ord[q].resize(nrow[q]);
+    for (int i = 0; i < nrow[q]; ++i) ord[q][i] = i;
+    std::stable_sort(ord[q].begin(), ord[q].end(), [&](int x, int y) { return lam[q][x] > lam[q][y]; });
+    for (int r = 0; r < nrow[q]; ++r) all.push_back({lam[q][ord[q][r]], q, r});
+  }
+  std::stable_sort(all.begin(), all.end(), [](const Cand& x, const Cand& y) {
+    if (x.lam != y.lam) return x.lam > y.lam;
+    if (x.q != y.q) return x.q < y.q;
+    return x.rank < y.rank;
+  });
+  auto T = std::make_unique<heff_trunc>();
+  const int nk = std::min<int>(d_keep, (int)all.size());
+  std::vector<int> kept(nq, 0);
+  for (int i = 0; i < (int)all.size(); ++i) {
+    if (i < nk) {
+      T->sing.push_back(std::sqrt(std::max(all[i].lam, 0.0)));
+      kept[all[i].q]++;
+    } else {
+      T->discarded += std::max(all[i].lam, 0.0);
+    }
+  }
+  T->n_kept = nk;
+  // new isometry: kept eigenvectors (descending) of every kept sector
+  std::vector<GatherJob> gj;
+  std::vector<int32_t> cols;
+  std::vector<size_t> col_start;
+  int64_t ioff = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    int q = job_q[j];
+    if (kept[q] == 0) continue;
+    T->nup.push_back(qlist[q].first);
+    T->ndn.push_back(qlist[q].second);
+    T->dim.push_back(kept[q]);
+    col_start.push_back(cols.size());
+    for (int r = 0; r < kept[q]; ++r) cols.push_back(ord[q][r]);
+    GatherJob g{};
+    g.v_off = moff[q];
+    g.out_off = ioff;
+    g.n = nrow[q];
+    g.ncol = kept[q];
+    gj.push_back(g);
+    ioff += (int64_t)nrow[q] * kept[q];
+  }
+  DevBuf dcols, dg;
+  upload(dcols, cols, s);
+  for (size_t j = 0; j < gj.size(); ++j) gj[j].cols = dcols.as<int32_t>() + col_start[j];
+  upload(dg, gj, s);
+  T->iso.alloc((size_t)std::max<int64_t>(ioff, 1) * sizeof(double));
+  T->iso_len = ioff;
+  HCHECK(launch_gather_columns(dg.as<GatherJob>(), (int)gj.size(), vec.as<double>(), T->iso.as<double>(), s));
+  HCHECK(hipStreamSynchronize(s));
+  *out = T.release();
+  ABI_END(ctx)
+}
+
+extern "C" int heff_trunc_info(const heff_trunc* t, int32_t* n_kept, double* discarded, int32_t* n_sect, int64_t* iso_len) {
+  if (!t) return HEFF_EINVAL;
+  if (n_kept) *n_kept = t->n_kept;
+  if (discarded) *discarded = t->discarded;
+  if (n_sect) *n_sect = (int32_t)t->dim.size();
+  if (iso_len) *iso_len = t->iso_len;
+  return HEFF_OK;
+}
+
+extern "C" int heff_trunc_get(heff_ctx* ctx, const heff_trunc* t, double* sing, int32_t* nup, int32_t* ndn,
+                              int32_t* dim, double* iso_dev) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!t) throw Error(HEFF_EINVAL, "null truncation");
+  if (sing) std::copy(t->sing.begin(), t->sing.end(), sing);
+  if (nup) std::copy(t->nup.begin(), t->nup.end(), nup);
+  if (ndn) std::copy(t->ndn.begin(), t->ndn.end(), ndn);
+  if (dim) std::copy(t->dim.begin(), t->dim.end(), dim);
+  if (iso_dev && t->iso_len) {
+    HCHECK(hipMemcpyAsync(iso_dev, t->iso.p, (size_t)t->iso_len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    HCHECK(hipStreamSynchronize(ctx->stream));
+  }
+  ABI_END(ctx)
+}
+
+extern "C" int heff_trunc_free(heff_trunc* t) {
+  delete t;
+  return HEFF_OK;
 }
 
 // ---------------------------------------------------------------- introspection for tests

@@ -47,7 +47,7 @@ struct Tile {
   int32_t a, e;
   int32_t t0, t1;
   int32_t ldOut;
-  int32_t pad;
+  int32_t prob;  // problem index in a batch (0 for a single problem)
 };
 static_assert(sizeof(Tile) == 32, "tile layout");
 
@@ -64,6 +64,12 @@ struct DiagTask {
   int64_t offL, offR;
   uint32_t flags;  // T_IDL, T_IDR, T_SELL, T_SELR
   uint32_t pad;
+};
+
+template <typename T>
+struct ProbBases {  // operator stores of one problem of a batch
+  const T* L[2];
+  const T* R[2];
 };
 
 template <typename T>
@@ -95,6 +101,26 @@ hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_wo
                                const uint16_t* Lhi[2], const uint16_t* Llo[2],
                                const uint16_t* Rhi[2], const uint16_t* Rlo[2],
                                const float* X, float* out, hipStream_t s);
+// grid[v]: persistent work-groups of variant v
+hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, const ProbBases<float>* pb,
+                                 const float* X, float* out, const int grid[kNumVariants], hipStream_t s);
+hipError_t launch_bf16x3_mfma(const Tile* tiles, const WorkSet& ws, const Task* tasks, const uint16_t* Lhi[2],
+                              const uint16_t* Llo[2], const uint16_t* Rhi[2], const uint16_t* Rlo[2], const float* X,
+                              float* out, hipStream_t s, hipEvent_t (*ev)[2] = nullptr);
+// symmetric eigenproblems of the truncation (one work-group each, n <= kMaxEig)
+constexpr int kMaxEig = 1024;
+struct EigJob {
+  int64_t off;  // element offset of the n x n matrix (and of its eigenvectors)
+  int32_t n;
+  int32_t pad;
+};
+struct GatherJob {
+  int64_t v_off, out_off;
+  const int32_t* cols;  // device array of ncol eigenvector column indices
+  int32_t n, ncol;
+};
+hipError_t launch_sym_jacobi(const EigJob* jobs, int n_jobs, double* A, double* V, hipStream_t s);
+hipError_t launch_gather_columns(const GatherJob* jobs, int n_jobs, const double* V, double* out, hipStream_t s);
 hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0,
                        const double* L1, const double* R0, const double* R1, double* out,
                        hipStream_t s);

@@ -69,18 +69,18 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
 };
 
+// One work item (64 rows of one output tile); no barriers inside, so a wave
+// whose rows lie outside the tile simply returns.
 template <typename T, int KS, int NT>
-__global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
-                                                  const Task* __restrict__ tasks, Bases<T> B) {
+__device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
+                                           const Bases<T>& B) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
-  const Work w = work[blockIdx.x];
-  const Tile tile = tiles[w.tile];
   const int wrow0 = w.row0 + wave * 16;
-  if (wrow0 >= tile.a) return;  // no barriers below: idle waves may leave
+  if (wrow0 >= tile.a) return;
   const int row = wrow0 + n;
   const bool rowok = row < tile.a;
   const int E = tile.e;
@@ -163,6 +163,52 @@ __global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles
       if (r < tile.a && col < E) B.out[tile.offOut + (int64_t)r * tile.ldOut + col] = acc[nt][i];
     }
   }
+}
+
+template <typename T, int KS, int NT>
+__global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+                                                  const Task* __restrict__ tasks, Bases<T> B) {
+  const Work w = work[blockIdx.x];
+  chain_item<T, KS, NT>(tiles[w.tile], w, tasks, B);
+}
+
+// Batched, persistent form: a fixed grid strides over the work items of
+// many independent problems (tile.prob selects the problem's operator
+// stores; Psi and the output of all problems share one base each).
+template <typename T, int KS, int NT>
+__global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+                                                        int64_t n_work, const Task* __restrict__ tasks,
+                                                        const ProbBases<T>* __restrict__ pb, const T* X, T* out) {
+  for (int64_t i = blockIdx.x; i < n_work; i += gridDim.x) {
+    const Work w = work[i];
+    const Tile tile = tiles[w.tile];
+    const ProbBases<T> q = pb[tile.prob];
+    Bases<T> B;
+    B.L[0] = q.L[0];
+    B.L[1] = q.L[1];
+    B.R[0] = q.R[0];
+    B.R[1] = q.R[1];
+    B.X[0] = B.X[1] = X;
+    B.out = out;
+    chain_item<T, KS, NT>(tile, w, tasks, B);
+  }
+}
+
+hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, const ProbBases<float>* pb,
+                                 const float* X, float* out, const int grid[kNumVariants], hipStream_t s) {
+  for (int v = kNumVariants - 1; v >= 0; --v) {
+    if (ws.n[v] <= 0) continue;
+    dim3 gr((unsigned)grid[v]), blk(256);
+    switch (v) {
+      case 0: hipLaunchKernelGGL((chain_mfma_batch<float, 8, 2>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      case 1: hipLaunchKernelGGL((chain_mfma_batch<float, 16, 4>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      case 2: hipLaunchKernelGGL((chain_mfma_batch<float, 32, 8>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      default: hipLaunchKernelGGL((chain_mfma_batch<float, 64, 16>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename T>
@@ -302,6 +348,206 @@ hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_wo
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ chained product, bf16 split (MFMA)
+// Same output-stationary structure as chain_mfma on v_mfma_f32_16x16x32_bf16
+// (K = 32 per instruction; lane l holds A[l%16][8(l/16)+j] and
+// B[8(l/16)+j][l%16], j = 0..7; result as the f32 16x16x4 instruction).
+// Every product a*b is formed as ah*bh + ah*bl + al*bh (three instructions,
+// FP32 accumulation).  Stage 1 sums over b with lane group g covering the
+// contiguous k range [8 g ks, 8 (g+1) ks) (ks = ceil(b/32) instructions);
+// two 16-column chunks of T = f op(L) op(X) (FP32, re-split into hi/lo)
+// form the 32-wide A operand of stage 2.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 bits2bf(uint16_t u) { return __builtin_bit_cast(__bf16, u); }
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf8_t& hi, bf8_t& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    uint16_t h = f2bf(x[j]);
+    hi[j] = bits2bf(h);
+    lo[j] = bits2bf(f2bf(x[j] - bf2f(h)));
+  }
+}
+
+__device__ __forceinline__ f4_t mma3(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl, f4_t c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+template <int KS8, int NT>
+__global__ __launch_bounds__(256) void chain_bf16x3_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+                                                         const Task* __restrict__ tasks, Bf16Args B) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const Work w = work[blockIdx.x];
+  const Tile tile = tiles[w.tile];
+  const int wrow0 = w.row0 + wave * 16;
+  if (wrow0 >= tile.a) return;  // no barriers below
+  const int row = wrow0 + n;
+  const bool rowok = row < tile.a;
+  const int E = tile.e;
+  f4_t acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = f4_t{0, 0, 0, 0};
+  for (int ti = tile.t0; ti < tile.t1; ++ti) {
+    const Task t = tasks[ti];
+    const uint32_t fl = t.flags;
+    const int b = t.b, c = t.c;
+    const int sl = (fl & T_SELL) ? 1 : 0, sr = (fl & T_SELR) ? 1 : 0;
+    const uint16_t* Lh = B.Lhi[sl] + t.offL;
+    const uint16_t* Ll = B.Llo[sl] + t.offL;
+    const uint16_t* Rh = B.Rhi[sr] + t.offR;
+    const uint16_t* Rl = B.Rlo[sr] + t.offR;
+    const float* X = B.X + t.offX;
+    const float f = (float)t.f;
+    const int ks = (b + 31) >> 5;
+    const bool direct = (fl & (T_IDL | T_IDX)) != 0;
+    const bool tl = fl & T_TL, tx = fl & T_TX, tr = fl & T_TR;
+    bf8_t Lrh[KS8], Lrl[KS8];
+    if (!direct) {
+#pragma unroll
+      for (int s8 = 0; s8 < KS8; ++s8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = g * 8 * ks + 8 * s8 + j;
+          uint16_t vh = 0, vl = 0;
+          if (s8 < ks && rowok && k < b) {
+            const int64_t o = tl ? (int64_t)k * t.ldL + row : (int64_t)row * t.ldL + k;
+            vh = Lh[o];
+            vl = Ll[o];
+          }
+          Lrh[s8][j] = bits2bf(vh);
+          Lrl[s8][j] = bits2bf(vl);
+        }
+      }
+    }
+    for (int c0 = 0; c0 < c; c0 += 32) {
+      f4_t Tc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int cb = c0 + 16 * h;
+        f4_t Tt = f4_t{0, 0, 0, 0};
+        if (direct) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int col = cb + 4 * g + r;
+            float v = 0.f;
+            if (rowok && col < c) {
+              if (fl & T_IDL) v = ld_op(X, tx, row, col, t.ldX);
+              else {
+                const int64_t o = tl ? (int64_t)col * t.ldL + row : (int64_t)row * t.ldL + col;
+                v = bf2f(Lh[o]) + bf2f(Ll[o]);
+              }
+            }
+            Tt[r] = v;
+          }
+        } else if (cb < c) {
+          const int m = cb + n;
+          const bool mok = m < c;
+#pragma unroll
+          for (int s8 = 0; s8 < KS8; ++s8) {
+            if (s8 < ks) {
+              float xv[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const int k = g * 8 * ks + 8 * s8 + j;
+                xv[j] = (mok && k < b) ? ld_op(X, tx, k, m, t.ldX) : 0.f;
+              }
+              bf8_t xh, xl;
+              split8(xv, xh, xl);
+              Tt = mma3(xh, xl, Lrh[s8], Lrl[s8], Tt);
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Tt[r] *= f;
+        Tc[h] = Tt;
+      }
+      float tv[8];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        tv[r] = Tc[0][r];
+        tv[4 + r] = Tc[1][r];
+      }
+      bf8_t th, tlo;
+      split8(tv, th, tlo);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (nt * 16 < E) {
+          const int col = nt * 16 + n;
+          bf8_t rh, rl;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int kk = (j < 4) ? c0 + 4 * g + j : c0 + 16 + 4 * g + (j - 4);
+            uint16_t vh = 0, vl = 0;
+            if (kk < c && col < E) {
+              if (fl & T_IDR) {
+                vh = (kk == col) ? (uint16_t)0x3f80 : (uint16_t)0;
+              } else {
+                const int64_t o = tr ? (int64_t)col * t.ldR + kk : (int64_t)kk * t.ldR + col;
+                vh = Rh[o];
+                vl = Rl[o];
+              }
+            }
+            rh[j] = bits2bf(vh);
+            rl[j] = bits2bf(vl);
+          }
+          acc[nt] = mma3(th, tlo, rh, rl, acc[nt]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int col = nt * 16 + n;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = wrow0 + 4 * g + r;
+      if (rr < tile.a && col < E) B.out[tile.offOut + (int64_t)rr * tile.ldOut + col] = acc[nt][r];
+    }
+  }
+}
+
+hipError_t launch_bf16x3_mfma(const Tile* tiles, const WorkSet& ws, const Task* tasks, const uint16_t* Lhi[2],
+                              const uint16_t* Llo[2], const uint16_t* Rhi[2], const uint16_t* Rlo[2], const float* X,
+                              float* out, hipStream_t s, hipEvent_t (*ev)[2]) {
+  Bf16Args a;
+  for (int i = 0; i < 2; ++i) {
+    a.Lhi[i] = Lhi[i];
+    a.Llo[i] = Llo[i];
+    a.Rhi[i] = Rhi[i];
+    a.Rlo[i] = Rlo[i];
+  }
+  a.X = X;
+  a.out = out;
+  for (int v = kNumVariants - 1; v >= 0; --v) {
+    if (ws.n[v] <= 0) continue;
+    if (ev && ev[v][0]) {
+      hipError_t e = hipEventRecord(ev[v][0], s);
+      if (e != hipSuccess) return e;
+    }
+    dim3 grid((unsigned)ws.n[v]), blk(256);
+    switch (v) {
+      case 0: hipLaunchKernelGGL((chain_bf16x3_mfma<1, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
+      case 1: hipLaunchKernelGGL((chain_bf16x3_mfma<2, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
+      case 2: hipLaunchKernelGGL((chain_bf16x3_mfma<4, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
+      default: hipLaunchKernelGGL((chain_bf16x3_mfma<8, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev && ev[v][1]) {
+      e = hipEventRecord(ev[v][1], s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------------ diagonal
 __global__ __launch_bounds__(256) void diag_kernel(const Tile* __restrict__ tiles, const DiagTask* __restrict__ tasks,
                                                    const double* L0, const double* L1, const double* R0,
@@ -325,6 +571,149 @@ hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks
                        const double* L1, const double* R0, const double* R1, double* out, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(diag_kernel, dim3((unsigned)n_tiles), dim3(256), 0, s, tiles, tasks, L0, L1, R0, R1, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ symmetric eigensolver (truncation)
+// One work-group per symmetric matrix A (n x n, row-major in global memory,
+// n <= kMaxEig): parallel cyclic Jacobi with the round-robin pair schedule;
+// on exit A's diagonal holds the eigenvalues and V the eigenvectors
+// (columns).  Sweeps stop when the off-diagonal Frobenius norm is below
+// 1e-15 of the total norm (at most 60 sweeps).
+
+__global__ __launch_bounds__(256) void sym_jacobi_kernel(const EigJob* __restrict__ jobs, double* __restrict__ A_all,
+                                                         double* __restrict__ V_all) {
+  __shared__ double cs[kMaxEig / 2], sn[kMaxEig / 2];
+  __shared__ int pp[kMaxEig / 2], qq[kMaxEig / 2];
+  __shared__ double red[256];
+  __shared__ int done;
+  const EigJob J = jobs[blockIdx.x];
+  const int n = J.n;
+  double* A = A_all + J.off;
+  double* V = V_all + J.off;
+  const int tid = threadIdx.x;
+  for (int64_t idx = tid; idx < (int64_t)n * n; idx += 256) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
+  __syncthreads();
+  const int K = (n + 1) & ~1;
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int64_t idx = tid; idx < (int64_t)n * n; idx += 256) {
+      const double a = A[idx];
+      tot += a * a;
+      if (idx / n != idx % n) off += a * a;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) done = (offs <= 1e-30 * red[0]) ? 1 : 0;
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < K - 1; ++r) {
+      for (int pr = tid; pr < K / 2; pr += 256) {
+        const int a = (pr == 0) ? 0 : 1 + ((pr - 1 + r) % (K - 1));
+        const int bq = 1 + ((K - 1 - pr - 1 + r) % (K - 1));
+        const int p = a < bq ? a : bq, q = a < bq ? bq : a;
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[(int64_t)p * n + q];
+          if (apq != 0.0) {
+            const double th = (A[(int64_t)q * n + q] - A[(int64_t)p * n + p]) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        cs[pr] = c;
+        sn[pr] = s;
+        pp[pr] = p;
+        qq[pr] = q < n ? q : p;
+      }
+      __syncthreads();
+      for (int64_t idx = tid; idx < (int64_t)(K / 2) * n; idx += 256) {
+        const int pr = (int)(idx / n), j = (int)(idx % n);
+        const int p = pp[pr], q = qq[pr];
+        if (p == q) continue;
+        const double c = cs[pr], s = sn[pr];
+        const double ap = A[(int64_t)p * n + j], aq = A[(int64_t)q * n + j];
+        A[(int64_t)p * n + j] = c * ap - s * aq;
+        A[(int64_t)q * n + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int64_t idx = tid; idx < (int64_t)(K / 2) * n; idx += 256) {
+        const int pr = (int)(idx / n), i = (int)(idx % n);
+        const int p = pp[pr], q = qq[pr];
+        if (p == q) continue;
+        const double c = cs[pr], s = sn[pr];
+        const double ap = A[(int64_t)i * n + p], aq = A[(int64_t)i * n + q];
+        A[(int64_t)i * n + p] = c * ap - s * aq;
+        A[(int64_t)i * n + q] = s * ap + c * aq;
+        const double vp = V[(int64_t)i * n + p], vq = V[(int64_t)i * n + q];
+        V[(int64_t)i * n + p] = c * vp - s * vq;
+        V[(int64_t)i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_sym_jacobi(const EigJob* jobs, int n_jobs, double* A, double* V, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sym_jacobi_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, A, V);
+  return hipGetLastError();
+}
+
+// Columns of the new isometry: out[r * ncol + j] = sign_j * V[r * n + col_j]
+// with sign_j making the largest-magnitude entry of the column positive.
+__global__ __launch_bounds__(256) void gather_columns_kernel(const GatherJob* __restrict__ jobs,
+                                                            const double* __restrict__ V_all, double* __restrict__ out) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const GatherJob J = jobs[blockIdx.x];
+  const double* V = V_all + J.v_off;
+  const int n = J.n;
+  for (int j = 0; j < J.ncol; ++j) {
+    const int col = J.cols[j];
+    double best = -1.0;
+    int idx = 0;
+    for (int r = threadIdx.x; r < n; r += 256) {
+      const double a = fabs(V[(int64_t)r * n + col]);
+      if (a > best) { best = a; idx = r; }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) {
+        const double o = bv[threadIdx.x + st];
+        const int oi = bi[threadIdx.x + st];
+        if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+          bv[threadIdx.x] = o;
+          bi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const double sg = V[(int64_t)bi[0] * n + col] < 0 ? -1.0 : 1.0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += 256) out[J.out_off + (int64_t)r * J.ncol + j] = sg * V[(int64_t)r * n + col];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_gather_columns(const GatherJob* jobs, int n_jobs, const double* V, double* out, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_columns_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, V, out);
   return hipGetLastError();
 }
 

@@ -64,13 +64,29 @@ _lib.heff_dav_free.argtypes = [_vp]
 _lib.heff_timing.argtypes = [_vp, _i]
 _lib.heff_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_task_stats_variant.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_truncate.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)]
+_lib.heff_trunc_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_trunc_get.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _vp]
+_lib.heff_trunc_free.argtypes = [_vp]
+_lib.heff_batch_layout.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_batch_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
+_lib.heff_batch_set_grid.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
+_lib.heff_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_batch_apply.argtypes = [_vp, _vp, _i]
+_lib.heff_batch_free.argtypes = [_vp]
 _lib.heff_debug_op.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
 _lib.heff_debug_op.restype = ctypes.c_int64
 
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
-            "heff_task_stats_variant")
+            "heff_task_stats_variant", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
+            "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
 
 
@@ -82,6 +98,7 @@ class HeffError(RuntimeError):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
 
 
 class Context:
@@ -214,6 +231,36 @@ class Blocks:
         self.ctx.check(_lib.heff_diag(self.ctx._h, self._h, _ptr(out)))
         return out
 
+    def truncate(self, psi, d_keep):
+        """Keep the d_keep largest singular values of psi over the enlarged
+        left sectors.  Returns dict(sing, discarded, tab {(nu, nd): dim},
+        iso: {(nu, nd): stacked matrix}) (isometry copied to the host)."""
+        import torch
+        if psi.dtype != torch.float64 or psi.numel() != self.n_elem or not psi.is_cuda:
+            raise ValueError("psi must be a float64 device tensor of %d elements" % self.n_elem)
+        h = _vp()
+        self.ctx.check(_lib.heff_truncate(self.ctx._h, self._h, _ptr(psi), int(d_keep), ctypes.byref(h)))
+        try:
+            nk = ctypes.c_int32()
+            disc = ctypes.c_double()
+            ns = ctypes.c_int32()
+            ln = ctypes.c_int64()
+            _lib.heff_trunc_info(h, ctypes.byref(nk), ctypes.byref(disc), ctypes.byref(ns), ctypes.byref(ln))
+            sing = np.empty(nk.value)
+            nu = np.empty(ns.value, dtype=np.int32)
+            nd = np.empty(ns.value, dtype=np.int32)
+            dm = np.empty(ns.value, dtype=np.int32)
+            iso = torch.empty(max(ln.value, 1), dtype=torch.float64, device=psi.device)
+            self.ctx.check(_lib.heff_trunc_get(self.ctx._h, h, sing.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               dm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(iso)))
+            flat = iso[: ln.value].cpu().numpy()
+        finally:
+            _lib.heff_trunc_free(h)
+        tab = {(int(a), int(b_)): int(d) for a, b_, d in zip(nu, nd, dm)}
+        return dict(sing=sing, discarded=disc.value, tab=tab, iso_flat=flat)
+
     def debug_op(self, side, kind, i=0, j=0):
         n = _lib.heff_debug_op(self._h, side, kind, i, j, None, 0)
         if n <= 0:
@@ -269,6 +316,61 @@ class Davidson:
 
     def __del__(self):
         if _finalizing():  # the HIP runtime may already be gone
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems (FP32 operands) in one persistent, graph-captured
+    launch per kernel variant.  x / y are the concatenated FP32 input and
+    output device vectors; views(i) gives problem i's slices."""
+
+    def __init__(self, ctx: Context, blocks):
+        import torch
+        self.ctx = ctx
+        self.blocks = list(blocks)
+        arr = (_vp * len(self.blocks))(*[b._h for b in self.blocks])
+        self._arr = arr
+        n = len(self.blocks)
+        offs = (ctypes.c_int64 * n)()
+        tot = ctypes.c_int64()
+        ctx.check(_lib.heff_batch_layout(arr, n, offs, ctypes.byref(tot)))
+        self.offsets = list(offs)
+        self.n_total = tot.value
+        self.x = torch.zeros(max(self.n_total, 1), dtype=torch.float32, device="cuda")
+        self.y = torch.zeros(max(self.n_total, 1), dtype=torch.float32, device="cuda")
+        h = _vp()
+        ctx.check(_lib.heff_batch_create(ctx._h, arr, n, _ptr(self.x), _ptr(self.y), ctypes.byref(h)))
+        self._h = h
+
+    def views(self, i):
+        o, n = self.offsets[i], self.blocks[i].n_elem
+        return self.x[o:o + n], self.y[o:o + n]
+
+    def set_grid(self, grid):
+        g = (ctypes.c_int32 * N_VARIANTS)(*grid)
+        self.ctx.check(_lib.heff_batch_set_grid(self._h, g))
+
+    def stats(self):
+        fl = ctypes.c_double()
+        g = (ctypes.c_int32 * N_VARIANTS)()
+        w = (ctypes.c_int64 * N_VARIANTS)()
+        self.ctx.check(_lib.heff_batch_stats(self._h, ctypes.byref(fl), g, w))
+        return dict(flops=fl.value, grid=list(g), work_items=list(w))
+
+    def apply(self, use_graph=True):
+        self.ctx.check(_lib.heff_batch_apply(self.ctx._h, self._h, 1 if use_graph else 0))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.heff_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        if _finalizing():
             return
         try:
             self.close()

@@ -202,3 +202,74 @@ def test_det_isometries_sampled_rows_n24(heff, ctx):
     ref = np.array([fci.row_dot(p.h, p.V, dets[i], basis, xs) for i in idx])
     scale = np.abs(ref).max()
     assert np.abs(y[idx] - ref).max() <= 1e-10 * scale
+
+
+def _iso_blocks(tab, old_tab, flat):
+    """Split the flat isometry of site k into {q: stacked matrix}."""
+    out, off = {}, 0
+    for q, d in tab.items():
+        rows = sum(old_tab.get((q[0] - synth.SITE_Q[s][0], q[1] - synth.SITE_Q[s][1]), 0) for s in range(4))
+        out[q] = flat[off: off + rows * d].reshape(rows, d)
+        off += rows * d
+    return out
+
+
+@pytest.mark.parametrize("N,D,keep,planted", [(8, 16, 20, True), (10, 32, 24, False), (12, 96, 80, False)])
+def test_truncation_matches_oracle(heff, ctx, N, D, keep, planted):
+    from oracle import svd
+    p = synth.make_problem(N, D, 3)
+    if planted:
+        from test_oracle_heff import _planted_psi
+        psi, _ = _planted_psi(p, np.random.default_rng(4))
+    else:
+        psi = synth.random_psi(p)
+    B = heff.Blocks(ctx, p)
+    got = B.truncate(_dev(psi), keep)
+    sing, disc, tab, iso = svd.truncate(p, psi, keep)
+    assert got["tab"] == tab
+    assert np.abs(got["sing"] - sing).max() <= 1e-10
+    assert abs(got["discarded"] - disc) <= 1e-12
+    gi = _iso_blocks(tab, p.tab_L, got["iso_flat"])
+    allsv = np.sort(np.concatenate([np.linalg.svd(m[0], compute_uv=False)
+                                    for m in svd.sector_matrices(p, psi).values()]))[::-1]
+    gap = allsv[keep - 1] - (allsv[keep] if keep < len(allsv) else 0.0)
+    for q, Q in iso.items():
+        G = gi[q]
+        assert np.abs(G.T @ G - np.eye(G.shape[1])).max() <= 1e-10
+        if gap > 1e-8:  # the kept subspace is unique
+            assert np.abs(G @ G.T - Q @ Q.T).max() <= 1e-8
+
+
+def test_batch_matches_single_and_oracle(heff, ctx):
+    # uneven problems (odd N -> S_z = 1/2), one persistent graph-captured
+    # launch; every problem equals its own single-problem FP32 product
+    # bitwise (same per-block task order) and the FP64 oracle within the
+    # FP32 bar; graph replays are bitwise stable
+    specs = [(8, 32, 101), (9, 48, 102), (10, 64, 103), (12, 96, 104), (11, 40, 105)]
+    probs = [synth.make_problem(N, D, sd) for N, D, sd in specs]
+    blocks = [heff.Blocks(ctx, p, precs=(0, 1)) for p in probs]
+    bt = heff.Batch(ctx, blocks)
+    psis = [synth.random_psi(p) for p in probs]
+    for i, psi in enumerate(psis):
+        bt.views(i)[0].copy_(torch.tensor(psi, dtype=torch.float32, device="cuda"))
+    bt.apply(use_graph=True)
+    torch.cuda.synchronize()
+    first = bt.y.clone()
+    for rep in range(3):
+        bt.y.zero_()
+        bt.apply(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.y, first)
+    bt.y.zero_()
+    bt.apply(use_graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(bt.y, first)
+    for i, (p, B, psi) in enumerate(zip(probs, blocks, psis)):
+        x32, y = bt.views(i)
+        single = torch.empty_like(x32)
+        B.apply(x32, single, prec=1)
+        torch.cuda.synchronize()
+        assert torch.equal(single, y)
+        y0 = block.apply(p, block.heff_terms(p), psi)
+        assert np.linalg.norm(y.double().cpu().numpy() - y0) <= 1e-5 * np.linalg.norm(y0)
+    bt.close()

@@ -124,3 +124,59 @@ def test_davidson_transient_is_rounding_sensitive(exact8):
     for _ in range(12):
         diffs.append(abs(a.step()[0] - b.step()[0]))
     assert max(diffs[:3]) < 1e-12 and max(diffs) > 1e-8
+
+
+def _planted_psi(p, rng):
+    """psi with a prescribed Schmidt spectrum in every enlarged-left sector:
+    M_Q' = U0 diag(sigma) V0^T with random orthonormal U0, V0."""
+    from oracle import svd
+    psi = np.zeros(synth.psi_size(p))
+    planted = []
+    mats = svd.sector_matrices(p, psi)
+    blocks = {(b[0], b[1], b[2]): b for b in synth.psi_blocks(p)}
+    for qp, (M, rows, cols) in mats.items():
+        r = min(M.shape)
+        U0, _ = np.linalg.qr(rng.standard_normal((M.shape[0], r)))
+        V0, _ = np.linalg.qr(rng.standard_normal((M.shape[1], r)))
+        sig = np.sort(rng.uniform(0.01, 1.0, r))[::-1]
+        planted += list(sig)
+        Mq = U0 @ np.diag(sig) @ V0.T
+        r0 = 0
+        for (s, qa, da) in rows:
+            c0 = 0
+            for (s1, qb, db) in cols:
+                b = blocks[(qa, s, s1)]
+                psi[b[6]: b[6] + da * db] = Mq[r0:r0 + da, c0:c0 + db].reshape(-1)
+                c0 += db
+            r0 += da
+    nrm = np.linalg.norm(psi)
+    return psi / nrm, np.sort(np.array(planted))[::-1] / nrm
+
+
+def test_truncation_recovers_planted_spectrum():
+    from oracle import svd
+    p = synth.make_problem(8, 16, 3)
+    psi, planted = _planted_psi(p, np.random.default_rng(4))
+    d_keep = 20
+    sing, disc, tab, iso = svd.truncate(p, psi, d_keep)
+    assert np.abs(sing - planted[:d_keep]).max() < 1e-12
+    assert abs(disc - np.sum(planted[d_keep:] ** 2)) < 1e-12
+    assert sum(tab.values()) == d_keep
+    for q, Q in iso.items():
+        assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-12
+
+
+def test_truncation_error_is_discarded_weight():
+    # Eckart-Young: projecting each sector matrix on the kept left vectors
+    # leaves exactly the discarded weight
+    from oracle import svd
+    p = synth.make_problem(10, 32, 6)
+    psi = synth.random_psi(p)
+    sing, disc, tab, iso = svd.truncate(p, psi, 24)
+    err = 0.0
+    for qp, (M, rows, cols) in svd.sector_matrices(p, psi).items():
+        Q = iso.get(qp)
+        P = M if Q is None else M - Q @ (Q.T @ M)
+        err += np.sum(P * P)
+    assert abs(err - disc) < 1e-12
+    assert abs(np.sum(sing ** 2) + disc - 1.0) < 1e-12
