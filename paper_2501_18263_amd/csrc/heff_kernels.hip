@@ -69,18 +69,36 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
 };
 
-// One work item (64 rows of one output tile); no barriers inside, so a wave
-// whose rows lie outside the tile simply returns.
+// One work item (64 rows of one output tile).  Per 16-column chunk of the
+// inner dimension c, the X chunk (b x 16) and the R chunk (16 x E) are
+// loaded cooperatively by all 256 threads (coalesced, every load of the
+// chunk in flight at once) into LDS shared by the four waves; each
+// 16-lane group of an MFMA operand read then covers one contiguous 128-byte
+// LDS row segment.  Waves whose rows lie outside the tile take part in the
+// loads and barriers only.
+template <typename T, int KS, int NT>
+struct ChainSmem {
+  static constexpr int KMAX = 4 * KS;   // largest inner dimension b
+  static constexpr int EMAX = 16 * NT;  // largest output width
+  T X[KMAX * 16];
+  T R[16 * EMAX];
+};
+
 template <typename T, int KS, int NT>
 __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
-                                           const Bases<T>& B) {
+                                           const Bases<T>& B, ChainSmem<T, KS, NT>& sm) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  constexpr int KMAX = 4 * KS;
+  constexpr int EMAX = 16 * NT;
+  constexpr int XPT = (KMAX * 16 + 255) / 256;
+  constexpr int RPT = (16 * EMAX + 255) / 256;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int wrow0 = w.row0 + wave * 16;
-  if (wrow0 >= tile.a) return;
+  const bool wave_on = wrow0 < tile.a;
   const int row = wrow0 + n;
   const bool rowok = row < tile.a;
   const int E = tile.e;
@@ -97,63 +115,94 @@ __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, cons
     const T f = (T)t.f;
     const int ks = (b + 3) >> 2;
     const bool direct = (fl & (T_IDL | T_IDX)) != 0;
+    const bool idr = (fl & T_IDR) != 0;
+    const bool tx = (fl & T_TX) != 0, tr = (fl & T_TR) != 0, tl = (fl & T_TL) != 0;
     T Lr[KS];
     if (!direct) {
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k = g * ks + s;
         T v = T(0);
-        if (s < ks && rowok && k < b) v = ld_op(L, fl & T_TL, row, k, t.ldL);
+        if (s < ks && rowok && k < b) v = ld_op(L, tl, row, k, t.ldL);
         Lr[s] = v;
       }
     }
     for (int c0 = 0; c0 < c; c0 += 16) {
+      T xr[XPT], rr[RPT];
+      if (!direct) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+          const int idx = tid + 256 * q;
+          const int k = idx >> 4, m = c0 + (idx & 15);
+          T v = T(0);
+          if (k < b && m < c) v = ld_op(X, tx, k, m, t.ldX);
+          xr[q] = v;
+        }
+      }
+      if (!idr) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int idx = tid + 256 * q;
+          // transposed storage: consecutive threads walk the stored row (j)
+          const int j = tr ? (idx & 15) : (idx / EMAX);
+          const int col = tr ? (idx >> 4) : (idx % EMAX);
+          T v = T(0);
+          if (col < E && c0 + j < c && j < 16) v = ld_op(R, tr, c0 + j, col, t.ldR);
+          rr[q] = v;
+        }
+      }
+      __syncthreads();
+      if (!direct) {
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+          const int idx = tid + 256 * q;
+          if (idx < KMAX * 16) sm.X[idx] = xr[q];
+        }
+      }
+      if (!idr) {
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int idx = tid + 256 * q;
+          const int j = tr ? (idx & 15) : (idx / EMAX);
+          const int col = tr ? (idx >> 4) : (idx % EMAX);
+          if (j < 16 && col < EMAX) sm.R[j * EMAX + col] = rr[q];
+        }
+      }
+      __syncthreads();
+      if (!wave_on) continue;
       v4 Tt = v4{0, 0, 0, 0};
       if (direct) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int col = c0 + M::row(i, g);
           T v = T(0);
-          if (rowok && col < c) {
-            if (fl & T_IDL) v = ld_op(X, fl & T_TX, row, col, t.ldX);
-            else v = ld_op(L, fl & T_TL, row, col, t.ldL);
-          }
+          if (rowok && col < c) v = (fl & T_IDL) ? ld_op(X, tx, row, col, t.ldX) : ld_op(L, tl, row, col, t.ldL);
           Tt[i] = v;
         }
       } else {
-        const int m = c0 + n;
-        const bool mok = m < c;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          if (s < ks) {
-            const int k = g * ks + s;
-            T xa = T(0);
-            if (mok && k < b) xa = ld_op(X, fl & T_TX, k, m, t.ldX);
-            Tt = M::run(xa, Lr[s], Tt);
-          }
-        }
+        for (int s = 0; s < KS; ++s)
+          if (s < ks) Tt = M::run(sm.X[(g * ks + s) * 16 + n], Lr[s], Tt);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) Tt[i] *= f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int j = c0 + M::row(i, g);
-        const bool jok = j < c;
+        const int j = M::row(i, g);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           if (nt * 16 < E) {
             const int col = nt * 16 + n;
-            T br = T(0);
-            if (jok && col < E) {
-              if (fl & T_IDR) br = (j == col) ? T(1) : T(0);
-              else br = ld_op(R, fl & T_TR, j, col, t.ldR);
-            }
+            T br;
+            if (idr) br = (c0 + j == col) ? T(1) : T(0);
+            else br = sm.R[j * EMAX + col];
             acc[nt] = M::run(Tt[i], br, acc[nt]);
           }
         }
       }
     }
   }
+  if (!wave_on) return;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int col = nt * 16 + n;
@@ -168,8 +217,9 @@ __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, cons
 template <typename T, int KS, int NT>
 __global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                   const Task* __restrict__ tasks, Bases<T> B) {
+  __shared__ ChainSmem<T, KS, NT> sm;
   const Work w = work[blockIdx.x];
-  chain_item<T, KS, NT>(tiles[w.tile], w, tasks, B);
+  chain_item<T, KS, NT>(tiles[w.tile], w, tasks, B, sm);
 }
 
 // Batched, persistent form: a fixed grid strides over the work items of
@@ -179,6 +229,7 @@ template <typename T, int KS, int NT>
 __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                         int64_t n_work, const Task* __restrict__ tasks,
                                                         const ProbBases<T>* __restrict__ pb, const T* X, T* out) {
+  __shared__ ChainSmem<T, KS, NT> sm;
   for (int64_t i = blockIdx.x; i < n_work; i += gridDim.x) {
     const Work w = work[i];
     const Tile tile = tiles[w.tile];
@@ -190,7 +241,8 @@ __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__
     B.R[1] = q.R[1];
     B.X[0] = B.X[1] = X;
     B.out = out;
-    chain_item<T, KS, NT>(tile, w, tasks, B);
+    chain_item<T, KS, NT>(tile, w, tasks, B, sm);
+    __syncthreads();  // LDS reuse by the next item
   }
 }
 

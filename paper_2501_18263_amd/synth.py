@@ -287,3 +287,16 @@ def random_psi(p: Problem, seed=None):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(psi_size(p))
     return x / np.linalg.norm(x)
+
+
+def batch_specs(n_problems=64, seed=4):
+    """(N, D, seed) of the batched workload: one generator draws
+    N ~ U{12..28} and D ~ U{128, 256, 512, 1024} per problem; problem i uses
+    integral seed 1000 + i (odd N gives S_z = +1/2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_problems):
+        n = int(rng.integers(12, 29))
+        d = int(rng.choice([128, 256, 512, 1024]))
+        out.append((n, d, 1000 + i))
+    return out
