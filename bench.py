@@ -171,8 +171,13 @@ def main():
     t_build = time.perf_counter() - t0
     st = B.stats()
     vst = B.variant_stats()
+    ist = B.issued_stats()
     F = st["flops"]
     log("build %.1fs  tasks %d  F_alg %.3e  bytes %s" % (t_build, st["n_tasks"], F, st["bytes"]))
+    for v in range(len(vst)):
+        if vst[v][1]:
+            log("variant %d: work-groups %d  F_alg %.3e  F_mfma %.3e (issue eff %.3f)  steps %d (longest group %d)" % (
+                v, vst[v][1], vst[v][0], ist[v][0], vst[v][0] / max(ist[v][0], 1.0), ist[v][1], ist[v][2]))
     x0 = torch.tensor(psi0, device="cuda")
 
     res = {}
@@ -237,7 +242,9 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
             "kernel": "chain_mfma variant %d (output blocks with largest dim <= %d)" % (v, [32, 64, 128, 256][v]),
-            "flops_per_launch": vst[v][0], "avg_launch_ms": avg_s * 1e3}
+            "flops_per_launch": vst[v][0], "avg_launch_ms": avg_s * 1e3,
+            "mfma_flops_per_launch": ist[v][0], "mfma_issue_efficiency": vst[v][0] / max(ist[v][0], 1.0),
+            "pipeline_steps_per_launch": ist[v][1], "pipeline_steps_longest_group": ist[v][2]}
     out = {
         "metric": "H_eff·ψ TFLOP/s and Davidson step time, FP64 vs mixed, N=40 D=4096",
         "value": hr["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

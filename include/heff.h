@@ -126,6 +126,13 @@ int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* flops, doubl
 int heff_timing(heff_ctx* ctx, int enable);
 int heff_timing_read(heff_ctx* ctx, double* ms, int64_t* launches);
 int heff_task_stats_variant(const heff_blocks* b, int v, double* flops, int64_t* work_items);
+/* Issue counts of the FP64/FP32 kernel of variant v per product: the flops
+ * of the matrix instructions it executes (the algorithmic flops plus the
+ * padding of every dimension to the 16-wide instruction tiles) and the
+ * number of pipeline steps summed over its work-groups (one step = one
+ * 16-wide slice of the inner index of op(L) op(X) or of the rows of op(R))
+ * and of its longest work-group (the critical path of the launch). */
+int heff_task_stats_issued(const heff_blocks* b, int v, double* mfma_flops, int64_t* steps, int64_t* max_steps);
 
 /* out = H_eff psi.  psi, out: device arrays of n_elem elements of the
  * precision's storage type (double for FP64, float for FP32 and BF16X3);

@@ -423,43 +423,58 @@ struct ChainPlan {
   std::vector<Task> tasks;
 };
 
+// Restrict a task to the range [m0, m0 + w) of its middle index c.  An
+// identity op(X) (b == c) keeps only the rows k in the same range, so b and
+// the columns of op(L) shrink with it; an identity op(R) stays the identity.
+static Task restrict_c(Task s, int m0, int w) {
+  if (s.flags & T_IDX) {
+    s.b = (uint16_t)w;
+    s.offL += (s.flags & T_TL) ? (int64_t)m0 * s.ldL : m0;
+  } else {
+    s.offX += (s.flags & T_TX) ? (int64_t)m0 * s.ldX : m0;
+  }
+  if (!(s.flags & T_IDR)) s.offR += (s.flags & T_TR) ? m0 : (int64_t)m0 * s.ldR;
+  s.c = (uint16_t)w;
+  return s;
+}
+
 // Split output tiles wider than kMaxDim into column slices and tasks whose
-// inner dimension b exceeds kMaxDim into k ranges (the partial products add
-// up in the output-stationary accumulation), so that every task fits the
-// register budget of the matrix-core kernels.
+// middle dimension c exceeds kMaxDim into ranges of c (the partial products
+// add up in the output-stationary accumulation), so that every task fits
+// the register budget of the matrix-core kernels (they hold T = op(L) op(X)
+// with c columns; the inner dimension b is streamed and unbounded).
 static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
   bool any = false;
   for (auto& t : tiles) any |= t.e > kMaxDim;
-  for (auto& k : tasks) any |= k.b > kMaxDim;
+  for (auto& k : tasks) any |= k.c > kMaxDim;
   if (!any) return;
   std::vector<Tile> nt;
   std::vector<Task> nk;
   for (const Tile& t : tiles) {
     for (int n0 = 0; n0 < std::max(t.e, 1); n0 += kMaxDim) {
       Tile u = t;
-      const int ew = std::min(kMaxDim, t.e - n0);
+      const int ew = std::max(std::min(kMaxDim, t.e - n0), 0);
       u.offOut = t.offOut + n0;
-      u.e = std::max(ew, 0);
+      u.e = ew;
       u.t0 = (int32_t)nk.size();
       for (int q = t.t0; q < t.t1; ++q) {
         Task s = tasks[q];
-        if (n0 > 0) {
-          if (s.flags & T_IDR) throw Error(HEFF_EINVAL, "internal: identity right operand in a split tile");
-          s.offR += (s.flags & T_TR) ? (int64_t)n0 * s.ldR : n0;
-        }
-        s.e = (uint16_t)u.e;
-        const bool direct = (s.flags & (T_IDL | T_IDX)) != 0;
-        if (direct || s.b <= kMaxDim) {
+        if (s.flags & T_IDR) {
+          // identity op(R) (c == e): the column slice [n0, n0 + ew) of the
+          // output takes the same range of c
+          if (s.c != t.e) throw Error(HEFF_EINVAL, "internal: identity right operand with c != e");
+          s = restrict_c(s, n0, ew);
+          s.e = (uint16_t)ew;
           nk.push_back(s);
           continue;
         }
-        for (int k0 = 0; k0 < s.b; k0 += kMaxDim) {
-          Task r = s;
-          r.b = (uint16_t)std::min(kMaxDim, s.b - k0);
-          r.offL += (s.flags & T_TL) ? (int64_t)k0 * s.ldL : k0;
-          r.offX += (s.flags & T_TX) ? k0 : (int64_t)k0 * s.ldX;
-          nk.push_back(r);
+        if (n0 > 0) s.offR += (s.flags & T_TR) ? (int64_t)n0 * s.ldR : n0;
+        s.e = (uint16_t)ew;
+        if (s.c <= kMaxDim) {
+          nk.push_back(s);
+          continue;
         }
+        for (int m0 = 0; m0 < s.c; m0 += kMaxDim) nk.push_back(restrict_c(s, m0, std::min(kMaxDim, s.c - m0)));
       }
       u.t1 = (int32_t)nk.size();
       nt.push_back(u);
@@ -469,20 +484,24 @@ static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
   tasks.swap(nk);
 }
 
-// largest dimension a tile's kernel must hold in registers
-static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
+// Largest dimension a tile's kernels hold in registers: e and c for the
+// FP64/FP32 kernels, also b for the bf16 kernel (with_b).
+static int tile_dim(const Tile& t, const std::vector<Task>& tasks, bool with_b = false) {
   int d = t.e;
-  for (int k = t.t0; k < t.t1; ++k)
-    if (!(tasks[k].flags & (T_IDL | T_IDX))) d = std::max<int>(d, tasks[k].b);
+  for (int k = t.t0; k < t.t1; ++k) {
+    d = std::max<int>(d, tasks[k].c);
+    if (with_b && !(tasks[k].flags & (T_IDL | T_IDX))) d = std::max<int>(d, tasks[k].b);
+  }
   return d;
 }
 
 // Work items of the matrix-core kernels, one list per variant (tiles taken
 // in the given order, each cut into kTileRows-row items).
 static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
-                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants]) {
+                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants],
+                       bool with_b = false) {
   for (int t : order) {
-    int v = variant_of(tile_dim(tiles[t], tasks));
+    int v = variant_of(tile_dim(tiles[t], tasks, with_b));
     for (int r = 0; r < tiles[t].a; r += kTileRows) lists[v].push_back({t, r});
   }
 }
@@ -915,6 +934,9 @@ struct heff_blocks {
   int64_t n_tiles = 0, n_tasks = 0, n_work = 0, n_dtasks = 0;
   double flops = 0.0, bytes[3] = {0, 0, 0};
   double vflops[heff::kNumVariants] = {0, 0, 0, 0};  // algorithmic flops per kernel variant
+  double vissued[heff::kNumVariants] = {0, 0, 0, 0};  // matrix-instruction flops of the FP64/FP32 kernel
+  int64_t vsteps[heff::kNumVariants] = {0, 0, 0, 0};  // pipeline steps summed over work-groups
+  int64_t vmaxsteps[heff::kNumVariants] = {0, 0, 0, 0};  // pipeline steps of the longest work-group
   // reduced-precision operand copies: [L store, L temps, R store, R temps]
   heff::DevBuf f32[4], bhi[4], blo[4];
 };
@@ -1229,12 +1251,26 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   for (int y : order)
     for (int r = 0; r < tiles[y].a; r += kPlainRows) work.push_back({y, r});
   std::vector<Work> lists[kNumVariants];
-  split_work(tiles, tasks, order, lists);
+  split_work(tiles, tasks, order, lists, true);
   B.mwork.upload_lists(lists, s);
   for (int y = 0; y < nb; ++y) {
     double fl = 0.0;
     for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
-    B.vflops[variant_of(tile_dim(tiles[y], tasks))] += fl;
+    const int v = variant_of(tile_dim(tiles[y], tasks, true));
+    B.vflops[v] += fl;
+    // what the FP64/FP32 kernel issues: per active 16-row wave, 4 ceil(c/16)
+    // MFMAs per stage-1 step (ceil(b/16) steps) and 4 ceil(e/16) per stage-2
+    // step (ceil(c/16) steps); every 64-row work-group takes every step
+    const int64_t waves = (tiles[y].a + 15) / 16, groups = (tiles[y].a + kTileRows - 1) / kTileRows;
+    const int64_t ne = (tiles[y].e + 15) / 16;
+    int64_t item_steps = 0;
+    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) {
+      const int64_t nb = (tasks[k].b + 15) / 16, nc = (tasks[k].c + 15) / 16;
+      B.vissued[v] += 2048.0 * 4.0 * (double)waves * (double)(nb * nc + nc * ne);
+      item_steps += nb + nc;
+    }
+    B.vsteps[v] += groups * item_steps;
+    B.vmaxsteps[v] = std::max(B.vmaxsteps[v], item_steps);
   }
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
   B.n_tiles = nb;
@@ -1521,6 +1557,15 @@ extern "C" int heff_task_stats_variant(const heff_blocks* b, int v, double* flop
   if (!b || v < 0 || v >= kNumVariants) return HEFF_EINVAL;
   if (flops) *flops = b->vflops[v];
   if (work_items) *work_items = b->mwork.ws.n[v];
+  return HEFF_OK;
+}
+
+extern "C" int heff_task_stats_issued(const heff_blocks* b, int v, double* mfma_flops, int64_t* steps,
+                                      int64_t* max_steps) {
+  if (!b || v < 0 || v >= kNumVariants) return HEFF_EINVAL;
+  if (mfma_flops) *mfma_flops = b->vissued[v];
+  if (steps) *steps = b->vsteps[v];
+  if (max_steps) *max_steps = b->vmaxsteps[v];
   return HEFF_OK;
 }
 

@@ -20,6 +20,15 @@ __device__ __forceinline__ T ld_op(const T* p, bool trans, int r, int c, int ld)
   return trans ? p[(int64_t)c * ld + r] : p[(int64_t)r * ld + c];
 }
 
+// b if c else a, by integer masking: a conditional choice between two
+// members of a private array must not become an indexed access to it
+// (that would place the array in scratch memory)
+template <typename T>
+__device__ __forceinline__ const T* pick(bool c, const T* a, const T* b) {
+  const uint64_t x = (uint64_t)a, y = (uint64_t)b, m = 0 - (uint64_t)c;
+  return (const T*)(x ^ ((x ^ y) & m));
+}
+
 // round-to-nearest-even float -> bf16 bits
 __device__ __forceinline__ uint16_t f2bf(float x) {
   uint32_t u = __float_as_uint(x);
@@ -35,21 +44,27 @@ constexpr int kAcc = kPlainRows * kMaxDim / kThreads;
 
 // ------------------------------------------------------------------ chained product (MFMA)
 // Matrix-core version: one work-group = 4 waves = 64 rows of one output
-// block; wave w owns rows [16w, 16w+16).  Per 16-column chunk of c:
-//   stage 1  T^T = op(X)^T op(L)^T on v_mfma_*_16x16x4, summing over b with
-//            the k order permuted so that lane group g covers the
-//            contiguous range [g*ks, (g+1)*ks): its result leaves register i
-//            of lane (g, n) holding T[row n][c0 + row(i, g)], which is exactly
-//            the A operand of stage 2 for k = c0 + row(i, g) (no LDS round
-//            trip);
-//   stage 2  acc += T op(R) over the same k order, op(R) row c0 + row(i, g).
-// The left operator strip op(L)[row][*] is kept in registers for the whole
-// task (it is reused by every chunk).  KS bounds ks = ceil(b/4), NT bounds
-// the 16-column output tiles.
+// block; wave w owns rows [16w, 16w+16).  A task  f op(L) op(X) op(R)  is
+// run as a sequence of steps over 16-wide slices:
+//   stage 1, one step per 16 values of the inner index k of op(L) op(X):
+//            T[rows][0..c) += op(L)[rows][k..k+16) op(X)[k..k+16)[0..c),
+//            with T held in registers as 16x16 MFMA result tiles;
+//   stage 2, one step per 16-row slice j of op(R):
+//            acc[rows][0..e) += f T[rows][j..j+16) op(R)[j..j+16)[0..e).
+// The op(X) and op(R) slices are shared by the four waves and pass through
+// LDS; each wave reads its own op(L) values straight into registers.  The
+// step loop is software pipelined: the global loads of step s+1 (the next
+// task's first slice when the task ends) are issued before the MFMAs of step
+// s and land in the other half of a double-buffered LDS area, so one
+// barrier per step suffices and the memory latency overlaps the matrix work.
+// Identity operands (flags T_IDL/T_IDX/T_IDR) are generated in place of
+// loads.  Stage-1 MFMA result registers are the stage-2 A operands without
+// any data movement: register i of lane (g, n) of tile cc holds
+// T[row n][16 cc + row(i, g)], the A operand for k = 16 cc + row(i, g).
 // Operand layout of both instructions: lane l holds A[l%16][l/16] and
 // B[l/16][l%16].  Result layout differs: register r of lane l holds
 // D[row(r, l/16)][l%16] with row = 4r + l/16 for f64 and 4(l/16) + r for f32
-// (checked on the device).
+// (checked on the device).  kmin(r) is the smallest row(r, g) over g.
 template <typename T>
 struct Mfma;
 template <>
@@ -59,6 +74,7 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
+  static __device__ __forceinline__ int kmin(int r) { return 4 * r; }
 };
 template <>
 struct Mfma<float> {
@@ -67,144 +83,331 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
+  static __device__ __forceinline__ int kmin(int r) { return r; }
 };
 
-// One work item (64 rows of one output tile).  Per 16-column chunk of the
-// inner dimension c, the X chunk (b x 16) and the R chunk (16 x E) are
-// loaded cooperatively by all 256 threads (coalesced, every load of the
-// chunk in flight at once) into LDS shared by the four waves; each
-// 16-lane group of an MFMA operand read then covers one contiguous 128-byte
-// LDS row segment.  Waves whose rows lie outside the tile take part in the
-// loads and barriers only.
-template <typename T, int KS, int NT>
+// LDS of one work-group: two step buffers (double buffering), each holding
+// one slice of op(X) [16][XST] (k-major) or of op(R) [16][RST], plus the
+// matching slice of op(L) [64][LST] for stage-1 steps.  The row strides are
+// chosen so that both the slice stores (16 lanes down a column when the
+// operand is stored transposed) and the operand reads (16 lanes along a row,
+// four row groups) spread over the banks.
+template <typename T, int NT>
 struct ChainSmem {
-  static constexpr int KMAX = 4 * KS;   // largest inner dimension b
-  static constexpr int EMAX = 16 * NT;  // largest output width
-  T X[KMAX * 16];
-  T R[16 * EMAX];
+  static constexpr int W = 16 * NT;  // largest c and e of the variant
+  static constexpr int XST = sizeof(T) == 8 ? W + 17 : W + 20;
+  static constexpr int RST = sizeof(T) == 8 ? W + 17 : W + 4;
+  static constexpr int LST = 17;
+  static constexpr int SL = 16 * (XST > RST ? XST : RST);
+  T buf[2][SL];
+  T lbuf[2][64 * LST];
 };
 
-template <typename T, int KS, int NT>
-__device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
-                                           const Bases<T>& B, ChainSmem<T, KS, NT>& sm) {
+// Step cursor: task index, stage (0/1) and slice index within the stage.
+struct Cursor {
+  int ti, ph, s;
+};
+
+// advance to the next step; false past the tile's last task.  `pre` holds
+// the descriptor of the task after cu.ti (loaded one task ahead).
+__device__ __forceinline__ bool next_step(Cursor& cu, Task& t, Task& pre, const Task* __restrict__ tasks, int t1) {
+  ++cu.s;
+  const int n = cu.ph == 0 ? (t.b + 15) >> 4 : (t.c + 15) >> 4;
+  if (cu.s < n) return true;
+  if (cu.ph == 0) {
+    cu.ph = 1;
+    cu.s = 0;
+    return true;
+  }
+  if (++cu.ti >= t1) return false;
+  t = pre;
+  pre = tasks[min(cu.ti + 1, t1 - 1)];
+  cu.ph = 0;
+  cu.s = 0;
+  return true;
+}
+
+// Per-thread coordinates inside the slices.  A 16 x W slice is walked in one
+// of two orders, chosen by which index is contiguous in global memory:
+//   k-contiguous (operand stored transposed): k = t15, m = t4 + 16 q;
+//   m-contiguous:                             k = tW + (256/W) q, m = tm.
+// The 64 x 16 op(L) slice: k-contiguous r = t4 + 16 q, k = t15; transposed
+// storage r = t63, k = t6 + 4 q.
+template <int W>
+struct Lane {
+  int t15, t4, tW, tm, t6, t63;
+  __device__ __forceinline__ explicit Lane(int tid)
+      : t15(tid & 15), t4(tid >> 4), tW(tid / W), tm(tid % W), t6(tid >> 6), t63(tid & 63) {}
+};
+
+// Staged values of one step for one thread: NT elements of the op(X) or
+// op(R) slice and 4 of the op(L) slice (stage 1 only).
+template <typename T, int NT>
+struct Stage {
+  T v[NT];
+  T l[4];
+};
+
+// Issue the global loads of one step; no loaded value is used here, so they
+// stay in flight during the matrix work of the current step.  Indices past
+// the operand's extent are clamped to its last row or column: such slice
+// entries only meet zeros of the other operand (op(L) columns past b and
+// op(R) rows past c are zeroed when stored) or feed rows/columns of the
+// result that are never written, so they need only be finite values.
+// Identity operands load nothing.
+template <typename T, int NT>
+__device__ __forceinline__ Stage<T, NT> load_step(const Task& t, const Bases<T>& B, const Cursor& cu,
+                                                  const Lane<16 * NT>& ln, int row0) {
+  constexpr int KQ = 256 / (16 * NT);
+  Stage<T, NT> st;
+  const uint32_t fl = t.flags;
+  const int base = 16 * cu.s;
+  if (cu.ph == 0) {
+    const int kmax = t.b - base - 1, cmax = t.c - 1;
+    if (!(fl & T_IDX)) {
+      const uint32_t ld = t.ldX;
+      if (fl & T_TX) {
+        const T* X = pick((fl & T_SELX) != 0, B.X[0], B.X[1]) + t.offX + base;
+        const uint32_t k = min(ln.t15, kmax);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) st.v[q] = X[(uint32_t)min(ln.t4 + 16 * q, cmax) * ld + k];
+      } else {
+        const T* X = pick((fl & T_SELX) != 0, B.X[0], B.X[1]) + t.offX + (int64_t)base * ld;
+        const uint32_t m = min(ln.tm, cmax);
+#pragma unroll
+        for (int q = 0; q < NT; ++q) st.v[q] = X[(uint32_t)min(ln.tW + KQ * q, kmax) * ld + m];
+      }
+    }
+    if (!(fl & T_IDL)) {
+      const uint32_t ld = t.ldL;
+      const int rmax = t.a - row0 - 1;
+      if (fl & T_TL) {
+        const T* L = pick((fl & T_SELL) != 0, B.L[0], B.L[1]) + t.offL + row0 + (int64_t)base * ld;
+        const uint32_t r = min(ln.t63, rmax);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st.l[q] = L[(uint32_t)min(ln.t6 + 4 * q, kmax) * ld + r];
+      } else {
+        const T* L = pick((fl & T_SELL) != 0, B.L[0], B.L[1]) + t.offL + (int64_t)row0 * ld + base;
+        const uint32_t kk = min(ln.t15, kmax);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st.l[q] = L[(uint32_t)min(ln.t4 + 16 * q, rmax) * ld + kk];
+      }
+    }
+  } else if (!(fl & T_IDR)) {
+    const int jmax = t.c - base - 1, emax = t.e - 1;
+    const uint32_t ld = t.ldR;
+    if (fl & T_TR) {
+      const T* R = pick((fl & T_SELR) != 0, B.R[0], B.R[1]) + t.offR + base;
+      const uint32_t j = min(ln.t15, jmax);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) st.v[q] = R[(uint32_t)min(ln.t4 + 16 * q, emax) * ld + j];
+    } else {
+      const T* R = pick((fl & T_SELR) != 0, B.R[0], B.R[1]) + t.offR + (int64_t)base * ld;
+      const uint32_t col = min(ln.tm, emax);
+#pragma unroll
+      for (int q = 0; q < NT; ++q) st.v[q] = R[(uint32_t)min(ln.tW + KQ * q, jmax) * ld + col];
+    }
+  }
+  return st;
+}
+
+// Write the values of one step to LDS buffer P: generate identity operands,
+// scale the op(L) slice by the task factor f and zero its columns past b,
+// zero the op(R) rows past c.
+template <typename T, int NT, int P>
+__device__ __forceinline__ void store_step(const Task& t, const Cursor& cu, const Lane<16 * NT>& ln, int row0,
+                                           const Stage<T, NT>& st, ChainSmem<T, NT>& sm) {
+  constexpr int W = 16 * NT, KQ = 256 / W;
+  using S = ChainSmem<T, NT>;
+  const uint32_t fl = t.flags;
+  const int base = 16 * cu.s;
+  T* buf = sm.buf[P];
+  if (cu.ph == 0) {
+    const int klim = t.b - base;
+    if (fl & T_IDX) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int kk = ln.tW + KQ * q;
+        buf[kk * S::XST + ln.tm] = T(base + kk == ln.tm ? 1 : 0);
+      }
+    } else if (fl & T_TX) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) buf[ln.t15 * S::XST + ln.t4 + 16 * q] = st.v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) buf[(ln.tW + KQ * q) * S::XST + ln.tm] = st.v[q];
+    }
+    T* lb = sm.lbuf[P];
+    const T f = (T)t.f;
+    if (fl & T_IDL) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = ln.t4 + 16 * q;
+        lb[r * S::LST + ln.t15] = (row0 + r == base + ln.t15) ? f : T(0);
+      }
+    } else if (fl & T_TL) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = ln.t6 + 4 * q;
+        lb[ln.t63 * S::LST + kk] = kk < klim ? st.l[q] * f : T(0);
+      }
+    } else {
+      const bool ok = ln.t15 < klim;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) lb[(ln.t4 + 16 * q) * S::LST + ln.t15] = ok ? st.l[q] * f : T(0);
+    }
+  } else {
+    const int jlim = t.c - base;
+    if (fl & T_IDR) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int j = ln.tW + KQ * q;
+        buf[j * S::RST + ln.tm] = T(base + j == ln.tm ? 1 : 0);
+      }
+    } else if (fl & T_TR) {
+      const bool ok = ln.t15 < jlim;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) buf[ln.t15 * S::RST + ln.t4 + 16 * q] = ok ? st.v[q] : T(0);
+    } else if (jlim >= 16) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) buf[(ln.tW + KQ * q) * S::RST + ln.tm] = st.v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int j = ln.tW + KQ * q;
+        buf[j * S::RST + ln.tm] = j < jlim ? st.v[q] : T(0);
+      }
+    }
+  }
+}
+
+// Stage-1 step on the first NC result tiles of T (columns 16 NC), stage-2
+// step of T tile CC on the first NE output tiles; NC, CC and NE are
+// compile-time so the matrix instructions form straight-line, in-place
+// accumulation chains with immediate LDS offsets.
+template <typename T, int NT, int NC, int P>
+__device__ __forceinline__ void stage1(typename Mfma<T>::v4 (&Tc)[NT], const ChainSmem<T, NT>& sm, int wave, int g,
+                                       int n) {
+  using S = ChainSmem<T, NT>;
+  const T* buf = sm.buf[P] + g * S::XST + n;
+  const T* lb = sm.lbuf[P] + (wave * 16 + n) * S::LST + g;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const T lv = lb[4 * j];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) Tc[cc] = Mfma<T>::run(buf[4 * j * S::XST + cc * 16], lv, Tc[cc]);
+  }
+}
+template <typename T, int NT, int NE, int CC, int P>
+__device__ __forceinline__ void stage2(typename Mfma<T>::v4 (&acc)[NT], const typename Mfma<T>::v4 (&Tc)[NT],
+                                       const ChainSmem<T, NT>& sm, int g, int n) {
+  using S = ChainSmem<T, NT>;
+  const T* buf = sm.buf[P] + n;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = Mfma<T>::row(i, g);
+#pragma unroll
+    for (int nt = 0; nt < NE; ++nt) acc[nt] = Mfma<T>::run(Tc[CC][i], buf[j * S::RST + nt * 16], acc[nt]);
+  }
+}
+template <typename T, int NT, int NC, int P>
+__device__ __forceinline__ void stage1_sw(int nc, typename Mfma<T>::v4 (&Tc)[NT], const ChainSmem<T, NT>& sm, int wave,
+                                          int g, int n) {
+  if constexpr (NC < NT) {
+    if (nc > NC) {
+      stage1_sw<T, NT, NC + 1, P>(nc, Tc, sm, wave, g, n);
+      return;
+    }
+  }
+  stage1<T, NT, NC, P>(Tc, sm, wave, g, n);
+}
+template <typename T, int NT, int NE, int CC, int P>
+__device__ __forceinline__ void stage2_sw(int s, typename Mfma<T>::v4 (&acc)[NT],
+                                          const typename Mfma<T>::v4 (&Tc)[NT], const ChainSmem<T, NT>& sm, int g,
+                                          int n) {
+  if constexpr (CC + 1 < NT) {
+    if (s > CC) {
+      stage2_sw<T, NT, NE, CC + 1, P>(s, acc, Tc, sm, g, n);
+      return;
+    }
+  }
+  stage2<T, NT, NE, CC, P>(acc, Tc, sm, g, n);
+}
+
+// One pipeline step on LDS buffer P: loads of step c1 into registers, matrix
+// work of step c0, LDS store of step c1 into buffer P^1, barrier.
+template <typename T, int NT, int NE, int P>
+__device__ __forceinline__ void pipe_step(const Tile& tile, const Task* __restrict__ tasks, const Bases<T>& B,
+                                          ChainSmem<T, NT>& sm, const Lane<16 * NT>& ln, int row0, bool wave_on,
+                                          int wave, int g, int n, typename Mfma<T>::v4 (&Tc)[NT],
+                                          typename Mfma<T>::v4 (&acc)[NT], bool& live, Cursor& c0, Task& t0,
+                                          Task& pre) {
+  using v4 = typename Mfma<T>::v4;
+  Cursor c1 = c0;
+  Task t1 = t0;
+  const bool more = next_step(c1, t1, pre, tasks, tile.t1);
+  Stage<T, NT> st;
+  if (more) st = load_step<T, NT>(t1, B, c1, ln, row0);
+  if (wave_on) {
+    if (c0.ph == 0) {
+      if (c0.s == 0) {
+#pragma unroll
+        for (int cc = 0; cc < NT; ++cc) Tc[cc] = v4{0, 0, 0, 0};
+      }
+      stage1_sw<T, NT, 1, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
+    } else {
+      stage2_sw<T, NT, NE, 0, P>(c0.s, acc, Tc, sm, g, n);
+    }
+  }
+  if (more) store_step<T, NT, P ^ 1>(t1, c1, ln, row0, st, sm);
+  __syncthreads();
+  live = more;
+  c0 = c1;
+  t0 = t1;
+}
+
+// One work item (64 rows of one output tile, NE 16-column output tiles).
+// Software pipeline: while step s computes from LDS buffer s%2, the global
+// loads of step s+1 are in flight and are written to the other buffer after
+// the matrix work; one barrier per step.  The loop body is unrolled twice so
+// that the buffer index is a compile-time constant.  Waves whose rows lie
+// outside the tile take part in the loads and barriers but skip the matrix
+// work.
+template <typename T, int NT, int NE>
+__device__ __forceinline__ void chain_item_e(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
+                                             const Bases<T>& B, ChainSmem<T, NT>& sm) {
   using M = Mfma<T>;
   using v4 = typename M::v4;
-  constexpr int KMAX = 4 * KS;
-  constexpr int EMAX = 16 * NT;
-  constexpr int XPT = (KMAX * 16 + 255) / 256;
-  constexpr int RPT = (16 * EMAX + 255) / 256;
   const int tid = threadIdx.x;
+  const Lane<16 * NT> ln(tid);
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int wrow0 = w.row0 + wave * 16;
   const bool wave_on = wrow0 < tile.a;
-  const int row = wrow0 + n;
-  const bool rowok = row < tile.a;
   const int E = tile.e;
-  v4 acc[NT];
+  v4 acc[NT], Tc[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) acc[nt] = v4{0, 0, 0, 0};
-  for (int ti = tile.t0; ti < tile.t1; ++ti) {
-    const Task t = tasks[ti];
-    const uint32_t fl = t.flags;
-    const int b = t.b, c = t.c;
-    const T* L = B.L[(fl & T_SELL) ? 1 : 0] + t.offL;
-    const T* X = B.X[(fl & T_SELX) ? 1 : 0] + t.offX;
-    const T* R = B.R[(fl & T_SELR) ? 1 : 0] + t.offR;
-    const T f = (T)t.f;
-    const int ks = (b + 3) >> 2;
-    const bool direct = (fl & (T_IDL | T_IDX)) != 0;
-    const bool idr = (fl & T_IDR) != 0;
-    const bool tx = (fl & T_TX) != 0, tr = (fl & T_TR) != 0, tl = (fl & T_TL) != 0;
-    T Lr[KS];
-    if (!direct) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int k = g * ks + s;
-        T v = T(0);
-        if (s < ks && rowok && k < b) v = ld_op(L, tl, row, k, t.ldL);
-        Lr[s] = v;
-      }
+  if (tile.t0 < tile.t1) {
+    Cursor c0{tile.t0, 0, 0};
+    Task t0 = tasks[tile.t0];
+    Task pre = tasks[min(tile.t0 + 1, tile.t1 - 1)];
+    {
+      const Stage<T, NT> st = load_step<T, NT>(t0, B, c0, ln, w.row0);
+      store_step<T, NT, 0>(t0, c0, ln, w.row0, st, sm);
     }
-    for (int c0 = 0; c0 < c; c0 += 16) {
-      T xr[XPT], rr[RPT];
-      if (!direct) {
-#pragma unroll
-        for (int q = 0; q < XPT; ++q) {
-          const int idx = tid + 256 * q;
-          const int k = idx >> 4, m = c0 + (idx & 15);
-          T v = T(0);
-          if (k < b && m < c) v = ld_op(X, tx, k, m, t.ldX);
-          xr[q] = v;
-        }
-      }
-      if (!idr) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int idx = tid + 256 * q;
-          // transposed storage: consecutive threads walk the stored row (j)
-          const int j = tr ? (idx & 15) : (idx / EMAX);
-          const int col = tr ? (idx >> 4) : (idx % EMAX);
-          T v = T(0);
-          if (col < E && c0 + j < c && j < 16) v = ld_op(R, tr, c0 + j, col, t.ldR);
-          rr[q] = v;
-        }
-      }
-      __syncthreads();
-      if (!direct) {
-#pragma unroll
-        for (int q = 0; q < XPT; ++q) {
-          const int idx = tid + 256 * q;
-          if (idx < KMAX * 16) sm.X[idx] = xr[q];
-        }
-      }
-      if (!idr) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int idx = tid + 256 * q;
-          const int j = tr ? (idx & 15) : (idx / EMAX);
-          const int col = tr ? (idx >> 4) : (idx % EMAX);
-          if (j < 16 && col < EMAX) sm.R[j * EMAX + col] = rr[q];
-        }
-      }
-      __syncthreads();
-      if (!wave_on) continue;
-      v4 Tt = v4{0, 0, 0, 0};
-      if (direct) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int col = c0 + M::row(i, g);
-          T v = T(0);
-          if (rowok && col < c) v = (fl & T_IDL) ? ld_op(X, tx, row, col, t.ldX) : ld_op(L, tl, row, col, t.ldL);
-          Tt[i] = v;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-          if (s < ks) Tt = M::run(sm.X[(g * ks + s) * 16 + n], Lr[s], Tt);
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Tt[i] *= f;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int j = M::row(i, g);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          if (nt * 16 < E) {
-            const int col = nt * 16 + n;
-            T br;
-            if (idr) br = (c0 + j == col) ? T(1) : T(0);
-            else br = sm.R[j * EMAX + col];
-            acc[nt] = M::run(Tt[i], br, acc[nt]);
-          }
-        }
-      }
+    __syncthreads();
+    bool live = true;
+    while (live) {
+      pipe_step<T, NT, NE, 0>(tile, tasks, B, sm, ln, w.row0, wave_on, wave, g, n, Tc, acc, live, c0, t0, pre);
+      if (!live) break;
+      pipe_step<T, NT, NE, 1>(tile, tasks, B, sm, ln, w.row0, wave_on, wave, g, n, Tc, acc, live, c0, t0, pre);
     }
   }
   if (!wave_on) return;
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
+  for (int nt = 0; nt < NE; ++nt) {
     const int col = nt * 16 + n;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -214,22 +417,43 @@ __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, cons
   }
 }
 
-template <typename T, int KS, int NT>
+// Output-width bucket of a tile: the kernel instance holds NE = NT/4, NT/2,
+// 3NT/4 or NT output tiles (at least one), the smallest that covers e.
+template <int NT, int Q>
+struct NeBucket {
+  static constexpr int value = (NT * Q) / 4 > 0 ? (NT * Q) / 4 : 1;
+};
+
+template <typename T, int NT>
+__device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
+                                           const Bases<T>& B, ChainSmem<T, NT>& sm) {
+  const int ne = (tile.e + 15) >> 4;
+  if (ne <= NeBucket<NT, 1>::value)
+    chain_item_e<T, NT, NeBucket<NT, 1>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 2>::value)
+    chain_item_e<T, NT, NeBucket<NT, 2>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 3>::value)
+    chain_item_e<T, NT, NeBucket<NT, 3>::value>(tile, w, tasks, B, sm);
+  else
+    chain_item_e<T, NT, NT>(tile, w, tasks, B, sm);
+}
+
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                   const Task* __restrict__ tasks, Bases<T> B) {
-  __shared__ ChainSmem<T, KS, NT> sm;
+  __shared__ ChainSmem<T, NT> sm;
   const Work w = work[blockIdx.x];
-  chain_item<T, KS, NT>(tiles[w.tile], w, tasks, B, sm);
+  chain_item<T, NT>(tiles[w.tile], w, tasks, B, sm);
 }
 
 // Batched, persistent form: a fixed grid strides over the work items of
 // many independent problems (tile.prob selects the problem's operator
 // stores; Psi and the output of all problems share one base each).
-template <typename T, int KS, int NT>
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                         int64_t n_work, const Task* __restrict__ tasks,
                                                         const ProbBases<T>* __restrict__ pb, const T* X, T* out) {
-  __shared__ ChainSmem<T, KS, NT> sm;
+  __shared__ ChainSmem<T, NT> sm;
   for (int64_t i = blockIdx.x; i < n_work; i += gridDim.x) {
     const Work w = work[i];
     const Tile tile = tiles[w.tile];
@@ -241,7 +465,7 @@ __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__
     B.R[1] = q.R[1];
     B.X[0] = B.X[1] = X;
     B.out = out;
-    chain_item<T, KS, NT>(tile, w, tasks, B, sm);
+    chain_item<T, NT>(tile, w, tasks, B, sm);
     __syncthreads();  // LDS reuse by the next item
   }
 }
@@ -252,10 +476,10 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
     if (ws.n[v] <= 0) continue;
     dim3 gr((unsigned)grid[v]), blk(256);
     switch (v) {
-      case 0: hipLaunchKernelGGL((chain_mfma_batch<float, 8, 2>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
-      case 1: hipLaunchKernelGGL((chain_mfma_batch<float, 16, 4>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
-      case 2: hipLaunchKernelGGL((chain_mfma_batch<float, 32, 8>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
-      default: hipLaunchKernelGGL((chain_mfma_batch<float, 64, 16>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      case 0: hipLaunchKernelGGL((chain_mfma_batch<float, 2>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      case 1: hipLaunchKernelGGL((chain_mfma_batch<float, 4>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      case 2: hipLaunchKernelGGL((chain_mfma_batch<float, 8>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
+      default: hipLaunchKernelGGL((chain_mfma_batch<float, 16>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -275,10 +499,10 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
     }
     dim3 grid((unsigned)ws.n[v]), blk(256);
     switch (v) {
-      case 0: hipLaunchKernelGGL((chain_mfma<T, 8, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
-      case 1: hipLaunchKernelGGL((chain_mfma<T, 16, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
-      case 2: hipLaunchKernelGGL((chain_mfma<T, 32, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
-      default: hipLaunchKernelGGL((chain_mfma<T, 64, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 0: hipLaunchKernelGGL((chain_mfma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 1: hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 2: hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      default: hipLaunchKernelGGL((chain_mfma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

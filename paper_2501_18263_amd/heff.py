@@ -11,8 +11,6 @@ import ctypes
 import os
 import sys
 
-_finalizing = sys.is_finalizing
-
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -64,6 +62,8 @@ _lib.heff_dav_free.argtypes = [_vp]
 _lib.heff_timing.argtypes = [_vp, _i]
 _lib.heff_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_task_stats_variant.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_task_stats_issued.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_truncate.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)]
 _lib.heff_trunc_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
@@ -74,6 +74,7 @@ _lib.heff_batch_layout.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.P
                                    ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
 _lib.heff_batch_set_grid.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
+_lib.heff_batch_io.argtypes = [_vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_apply.argtypes = [_vp, _vp, _i]
@@ -84,7 +85,7 @@ _lib.heff_debug_op.restype = ctypes.c_int64
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
-            "heff_task_stats_variant", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_task_stats_variant", "heff_task_stats_issued", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
@@ -136,8 +137,8 @@ class Context:
             _lib.heff_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the HIP runtime may already be gone
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():  # the HIP runtime may already be gone
             return
         try:
             self.close()
@@ -216,6 +217,18 @@ class Blocks:
             out.append((fl.value, nw.value))
         return out
 
+    def issued_stats(self):
+        """[(matrix-instruction flops, pipeline steps, steps of the longest
+        work-group)] per kernel variant of the FP64/FP32 kernel."""
+        out = []
+        for v in range(N_VARIANTS):
+            fl = ctypes.c_double()
+            ns = ctypes.c_int64()
+            mx = ctypes.c_int64()
+            self.ctx.check(_lib.heff_task_stats_issued(self._h, v, ctypes.byref(fl), ctypes.byref(ns), ctypes.byref(mx)))
+            out.append((fl.value, ns.value, mx.value))
+        return out
+
     def apply(self, psi, out, prec=FP64):
         """out = H_eff psi (device tensors: float64 for FP64, float32 otherwise)."""
         import torch
@@ -276,8 +289,8 @@ class Blocks:
             _lib.heff_blocks_free(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the HIP runtime may already be gone
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():  # the HIP runtime may already be gone
             return
         try:
             self.close()
@@ -314,8 +327,8 @@ class Davidson:
             _lib.heff_dav_free(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():  # the HIP runtime may already be gone
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():  # the HIP runtime may already be gone
             return
         try:
             self.close()
@@ -345,6 +358,16 @@ class Batch:
         h = _vp()
         ctx.check(_lib.heff_batch_create(ctx._h, arr, n, _ptr(self.x), _ptr(self.y), ctypes.byref(h)))
         self._h = h
+        if self.io() != (self.offsets, self.n_total):
+            raise HeffError(-1, "batch layout and batch object disagree")
+
+    def io(self):
+        """(offsets, n_total) of the concatenated input/output vectors as the
+        batch object holds them."""
+        po = ctypes.POINTER(ctypes.c_int64)()
+        tot = ctypes.c_int64()
+        self.ctx.check(_lib.heff_batch_io(self._h, ctypes.byref(po), ctypes.byref(tot)))
+        return [po[i] for i in range(len(self.blocks))], tot.value
 
     def views(self, i):
         o, n = self.offsets[i], self.blocks[i].n_elem
@@ -369,8 +392,8 @@ class Batch:
             _lib.heff_batch_free(self._h)
             self._h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():
             return
         try:
             self.close()

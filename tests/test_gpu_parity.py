@@ -185,9 +185,13 @@ def test_mixed_precision_davidson_energy(heff, ctx, prec):
     assert abs(e_corr - e64) <= 1e-6
 
 
-def test_det_isometries_sampled_rows_n24(heff, ctx):
-    # 0/1 isometries: every output entry is a determinant row of H_FCI
-    p = synth.make_problem(24, 1024, 2, iso_kind="det")
+@pytest.mark.parametrize("D", [1024, 4096])
+def test_det_isometries_sampled_rows_n24(heff, ctx, D):
+    # 0/1 isometries: every output entry is a determinant row of H_FCI.
+    # At D=4096 the bond after six sites holds a 400-dim sector, so the
+    # renormalization products exercise the column and middle-index splits
+    # of blocks wider than the kernels' register tiles.
+    p = synth.make_problem(24, D, 2, iso_kind="det")
     B = heff.Blocks(ctx, p)
     psi = synth.random_psi(p)
     y = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
