@@ -183,6 +183,40 @@ int heff_batch_stats(const heff_batch* b, double* flops, int32_t* grid /* [4] */
 int heff_batch_apply(heff_ctx* ctx, heff_batch* b, int use_graph);
 int heff_batch_free(heff_batch* b);
 
+/* Energy and its gradients (the orbital-rotation step of Sec. II.B works
+ * with derivatives of the two-site energy at fixed MPS isometries).
+ *
+ * heff_energy(): *E = <psi|H_eff|psi> (psi: device, n_elem elements of the
+ * precision's type; FP64 or FP32 operands; FP64 accumulation of the dot
+ * product).  Synchronizes the stream.
+ *
+ * heff_energy_backward(): reverse mode of E, scaled by gE (the upstream
+ * gradient).  dpsi (device, n_elem, may be NULL) = 2 gE H_eff psi.  dL and
+ * dR (device, may be NULL) receive dE/d(operator arena entries) of the left
+ * and right blocks, each laid out as the concatenation [store | temporaries]
+ * of heff_op_arena() (the operands exactly as the product's tasks read them:
+ * the renormalized operators of the block and the linear combinations of
+ * them that the terms use); entries no task reads are zero.  FP64 or FP32,
+ * the same precision for psi and all outputs.  Asynchronous.
+ *
+ * heff_op_arena(): device pointers and element counts of the four operand
+ * arenas [left store, left temporaries, right store, right temporaries] in
+ * precision prec (library-owned; valid while the blocks live).
+ *
+ * heff_kappa_gradient(): g[i] = dE/dkappa_xy for (x, y) = pairs[2i],
+ * pairs[2i+1] (host array), where the orbitals are rotated by U = exp(K),
+ * K = sum kappa_xy (E_xy - E_yx), h -> U^T h U, V -> (U x U x U x U)^T V,
+ * psi (device, FP64) and the isometries of p held fixed.  E is linear in
+ * the integrals, so g_xy is computed exactly as E with the first-order
+ * integral change of the rotation: one block build and one product per
+ * pair.  Synchronizes the stream. */
+int heff_energy(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double* E);
+int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double gE, void* dpsi,
+                         void* dL, void* dR);
+int heff_op_arena(const heff_blocks* b, int prec, void* ptr[4], int64_t n_elem[4]);
+int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
+                        const int32_t* pairs, double* g);
+
 /* Davidson eigensolver for the lowest eigenpair of H_eff (the Diag_H step).
  * m_max in [3, 29] basis vectors, restart to {Ritz vector, previous Ritz
  * vector}; converged when ||r|| <= tol*|theta|.  psi0: device, n_elem

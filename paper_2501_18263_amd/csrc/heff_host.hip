@@ -939,6 +939,15 @@ struct heff_blocks {
   int64_t vmaxsteps[heff::kNumVariants] = {0, 0, 0, 0};  // pipeline steps of the longest work-group
   // reduced-precision operand copies: [L store, L temps, R store, R temps]
   heff::DevBuf f32[4], bhi[4], blo[4];
+  // backward: task tables of the operand gradients (0: left, 1: right
+  // operator arenas), built on first use; scratch of heff_energy
+  struct GradPlan {
+    heff::DevBuf tiles, tasks;
+    heff::DevWorkSet work;
+    bool ready = false;
+  };
+  mutable GradPlan grad[2];
+  mutable heff::DevBuf escratch;
 };
 
 namespace heff {
@@ -1974,4 +1983,325 @@ extern "C" int64_t heff_debug_op(const heff_blocks* b, int side, int kind, int i
       return -2;
   }
   return L.size;
+}
+
+// ====================================================================== backward
+namespace heff {
+
+// Task tables of dE/d(operator arena) for E = <psi|H_eff|psi>.  Every product
+// task  out_y += f op(L) op(X) op(R)  (X a block of psi) contributes
+// E_t = f <psi_y, op(L) op(X) op(R)>, whose gradient is
+//   d/d op(L) = f psi_y op(R)^T op(X)^T,   d/d op(R) = f op(X)^T op(L)^T psi_y,
+// taken back to the storage orientation of the operand block.  Each stored
+// block becomes one output tile (all tasks that use it, in either
+// orientation, accumulate into it), and each contribution is again a
+// chained product, so the forward kernels run it.  Launch bases:
+// L[*] = R[*] = psi; X[0..1] = the other side's store and temporaries.
+static void make_grad_plan(const heff_blocks& B, int side, hipStream_t s) {
+  auto& G = B.grad[side];
+  const bool left = side == 0;
+  const int64_t n0 = left ? B.L->store.total : B.R->store.total;
+  std::map<std::pair<int, int64_t>, int> tile_of;
+  std::vector<Tile> tiles;
+  std::vector<std::vector<Task>> per;
+  const int nb = (int)B.h_tiles.size();
+  for (int y = 0; y < nb; ++y) {
+    const Tile& ty = B.h_tiles[y];
+    const int64_t py = ty.offOut;  // psi_y block (a x e, row stride e)
+    for (int k = ty.t0; k < ty.t1; ++k) {
+      const Task& t = B.h_tasks[k];
+      const uint32_t fl = t.flags;
+      const bool tl = fl & T_TL, tx = fl & T_TX, tr = fl & T_TR;
+      if (left ? (fl & T_IDL) : (fl & T_IDR)) continue;
+      const int sel = left ? ((fl & T_SELL) ? 1 : 0) : ((fl & T_SELR) ? 1 : 0);
+      const int64_t off = left ? t.offL : t.offR;
+      int rows, cols, ld;
+      if (left) {
+        rows = tl ? t.b : t.a;
+        cols = tl ? t.a : t.b;
+        ld = t.ldL;
+      } else {
+        rows = tr ? t.e : t.c;
+        cols = tr ? t.c : t.e;
+        ld = t.ldR;
+      }
+      auto key = std::make_pair(sel, off);
+      auto it = tile_of.find(key);
+      int id;
+      if (it == tile_of.end()) {
+        id = (int)tiles.size();
+        tile_of[key] = id;
+        Tile u{};
+        u.offOut = off + (sel ? n0 : 0);
+        u.a = rows;
+        u.e = cols;
+        u.ldOut = ld;
+        tiles.push_back(u);
+        per.emplace_back();
+      } else {
+        id = it->second;
+        if (tiles[id].a != rows || tiles[id].e != cols || tiles[id].ldOut != ld)
+          throw Error(HEFF_EINVAL, "internal: one operator block used with two shapes");
+      }
+      Task g{};
+      g.f = t.f;
+      uint32_t gf = 0;
+      if (left) {
+        // middle operand: op(R) or its transpose, from the right arenas
+        gf |= (fl & T_SELR) ? T_SELX : 0u;
+        gf |= (fl & T_IDR) ? T_IDX : 0u;
+        g.offX = t.offR;
+        g.ldX = t.ldR;
+        if (!tl) {  // (a x b) += f psi_y op(R)^T op(X)^T
+          g.a = t.a; g.b = t.e; g.c = t.c; g.e = t.b;
+          g.offL = py; g.ldL = t.e;
+          if (!tr) gf |= T_TX;
+          g.offR = t.offX; g.ldR = t.ldX;
+          if (!tx) gf |= T_TR;
+          if (fl & T_IDX) gf |= T_IDR;
+        } else {  // (b x a) += f op(X) op(R) psi_y^T
+          g.a = t.b; g.b = t.c; g.c = t.e; g.e = t.a;
+          g.offL = t.offX; g.ldL = t.ldX;
+          if (tx) gf |= T_TL;
+          if (fl & T_IDX) gf |= T_IDL;
+          if (tr) gf |= T_TX;
+          g.offR = py; g.ldR = t.e;
+          gf |= T_TR;
+        }
+      } else {
+        gf |= (fl & T_SELL) ? T_SELX : 0u;
+        gf |= (fl & T_IDL) ? T_IDX : 0u;
+        g.offX = t.offL;
+        g.ldX = t.ldL;
+        if (!tr) {  // (c x e) += f op(X)^T op(L)^T psi_y
+          g.a = t.c; g.b = t.b; g.c = t.a; g.e = t.e;
+          g.offL = t.offX; g.ldL = t.ldX;
+          if (!tx) gf |= T_TL;
+          if (fl & T_IDX) gf |= T_IDL;
+          if (!tl) gf |= T_TX;
+          g.offR = py; g.ldR = t.e;
+        } else {  // (e x c) += f psi_y^T op(L) op(X)
+          g.a = t.e; g.b = t.a; g.c = t.b; g.e = t.c;
+          g.offL = py; g.ldL = t.e;
+          gf |= T_TL;
+          if (tl) gf |= T_TX;
+          g.offR = t.offX; g.ldR = t.ldX;
+          if (tx) gf |= T_TR;
+          if (fl & T_IDX) gf |= T_IDR;
+        }
+      }
+      g.flags = (uint16_t)gf;
+      per[id].push_back(g);
+    }
+  }
+  std::vector<Task> tasks;
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    tiles[i].t0 = (int32_t)tasks.size();
+    tasks.insert(tasks.end(), per[i].begin(), per[i].end());
+    tiles[i].t1 = (int32_t)tasks.size();
+  }
+  if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "gradient task table too large");
+  split_large(tiles, tasks);
+  std::vector<int> order(tiles.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::vector<double> cost(tiles.size(), 0.0);
+  for (size_t i = 0; i < tiles.size(); ++i)
+    for (int k = tiles[i].t0; k < tiles[i].t1; ++k) cost[i] += task_flops(tasks[k]) / std::max(1, tiles[i].a);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<Work> lists[kNumVariants];
+  split_work(tiles, tasks, order, lists);
+  upload(G.tiles, tiles, s);
+  upload(G.tasks, tasks, s);
+  G.work.upload_lists(lists, s);
+  HCHECK(hipStreamSynchronize(s));
+  G.ready = true;
+}
+
+// device pointers of the four operand arenas [L store, L temps, R store,
+// R temps] in the given precision, and their element counts
+static void arenas(const heff_blocks& B, int prec, void* p[4], int64_t n[4]) {
+  n[0] = B.L->store.total;
+  n[1] = B.Ltmp.tmp.total;
+  n[2] = B.R->store.total;
+  n[3] = B.Rtmp.tmp.total;
+  if (prec == HEFF_FP64) {
+    p[0] = B.L->store.dev.p;
+    p[1] = B.Ltmp.tmp.dev.p;
+    p[2] = B.R->store.dev.p;
+    p[3] = B.Rtmp.tmp.dev.p;
+  } else if (prec == HEFF_FP32) {
+    if (!(B.prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
+    for (int i = 0; i < 4; ++i) p[i] = B.f32[i].p;
+  } else {
+    throw Error(HEFF_ENOTSUP, "gradients are available in FP64 and FP32");
+  }
+}
+
+template <typename T>
+static void run_grad(const heff_blocks& B, int side, void* const ar[4], const void* psi, void* dout, hipStream_t s) {
+  const auto& G = B.grad[side];
+  Bases<T> bs{};
+  bs.L[0] = bs.L[1] = static_cast<const T*>(psi);
+  bs.R[0] = bs.R[1] = static_cast<const T*>(psi);
+  bs.X[0] = static_cast<const T*>(ar[side == 0 ? 2 : 0]);
+  bs.X[1] = static_cast<const T*>(ar[side == 0 ? 3 : 1]);
+  bs.out = static_cast<T*>(dout);
+  if constexpr (sizeof(T) == 8)
+    HCHECK(launch_mfma_f64(G.tiles.as<Tile>(), G.work.ws, G.tasks.as<Task>(), bs, s));
+  else
+    HCHECK(launch_mfma_f32(G.tiles.as<Tile>(), G.work.ws, G.tasks.as<Task>(), bs, s));
+}
+
+static hipError_t launch_apply_prec(const heff_blocks& B, int prec, const void* psi, void* out, hipStream_t s) {
+  void* ar[4];
+  int64_t n[4];
+  arenas(B, prec, ar, n);
+  if (prec == HEFF_FP64) {
+    Bases<double> bs{};
+    for (int i = 0; i < 2; ++i) {
+      bs.L[i] = static_cast<const double*>(ar[i]);
+      bs.R[i] = static_cast<const double*>(ar[2 + i]);
+    }
+    bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
+    bs.out = static_cast<double*>(out);
+    return launch_mfma_f64(B.d_tiles.as<Tile>(), B.mwork.ws, B.d_tasks.as<Task>(), bs, s);
+  }
+  Bases<float> bs{};
+  for (int i = 0; i < 2; ++i) {
+    bs.L[i] = static_cast<const float*>(ar[i]);
+    bs.R[i] = static_cast<const float*>(ar[2 + i]);
+  }
+  bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
+  bs.out = static_cast<float*>(out);
+  return launch_mfma_f32(B.d_tiles.as<Tile>(), B.mwork.ws, B.d_tasks.as<Task>(), bs, s);
+}
+
+// first-order change of the integrals under the orbital rotation generated
+// by K = E_xy - E_yx: dh = K^T h + h K, dV_ijkl = sum over the four index
+// positions of K_ai V_(i -> a)
+static void rotation_derivative(const Ints& I, int x, int y, std::vector<double>& dh, std::vector<double>& dV) {
+  const int n = I.n;
+  auto K = [&](int a, int i) { return (a == x && i == y) ? 1.0 : (a == y && i == x) ? -1.0 : 0.0; };
+  dh.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int a : {x, y}) v += K(a, i) * I.h[(size_t)a * n + j] + I.h[(size_t)i * n + a] * K(a, j);
+      dh[(size_t)i * n + j] = v;
+    }
+  auto V = [&](int i, int j, int k, int l) { return I.V[(((size_t)i * n + j) * n + k) * n + l]; };
+  dV.assign((size_t)n * n * n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k)
+        for (int l = 0; l < n; ++l) {
+          double v = 0.0;
+          for (int a : {x, y}) {
+            v += K(a, i) * V(a, j, k, l) + K(a, j) * V(i, a, k, l) + K(a, k) * V(i, j, a, l) + K(a, l) * V(i, j, k, a);
+          }
+          dV[(((size_t)i * n + j) * n + k) * n + l] = v;
+        }
+}
+
+}  // namespace heff
+
+extern "C" int heff_op_arena(const heff_blocks* b, int prec, void* ptr[4], int64_t n_elem[4]) {
+  if (!b || !ptr || !n_elem) return HEFF_EINVAL;
+  try {
+    heff::arenas(*b, prec, ptr, n_elem);
+  } catch (const heff::Error& e) {
+    return e.code;
+  }
+  return HEFF_OK;
+}
+
+extern "C" int heff_energy(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double* E) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !E) throw Error(HEFF_EINVAL, "null argument");
+  if (prec != HEFF_FP64 && prec != HEFF_FP32) throw Error(HEFF_ENOTSUP, "energy is available in FP64 and FP32");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const size_t es = prec == HEFF_FP64 ? 8 : 4;
+  const size_t hbytes = ((b->n_elem * es + 255) / 256) * 256;  // H psi, then the reduction partials
+  const size_t need = hbytes + (kRedBlocks + 1) * sizeof(double);
+  if (b->escratch.bytes < need) b->escratch.alloc(need);
+  char* base = b->escratch.as<char>();
+  void* hp = base;
+  double* red = reinterpret_cast<double*>(base + hbytes);
+  HCHECK(launch_apply_prec(*b, prec, psi, hp, s));
+  if (prec == HEFF_FP64)
+    HCHECK(launch_dot_f64(static_cast<const double*>(psi), static_cast<const double*>(hp), b->n_elem, red + kRedBlocks,
+                          red, s));
+  else
+    HCHECK(launch_dot_f32(static_cast<const float*>(psi), static_cast<const float*>(hp), b->n_elem, red + kRedBlocks,
+                          red, s));
+  HCHECK(hipMemcpyAsync(E, red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  ABI_END(ctx)
+}
+
+extern "C" int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double gE,
+                                    void* dpsi, void* dL, void* dR) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi) throw Error(HEFF_EINVAL, "null argument");
+  if (prec != HEFF_FP64 && prec != HEFF_FP32) throw Error(HEFF_ENOTSUP, "gradients are available in FP64 and FP32");
+  if (dpsi == psi) throw Error(HEFF_EINVAL, "psi and dpsi alias");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  void* ar[4];
+  int64_t n[4];
+  arenas(*b, prec, ar, n);
+  const bool f64 = prec == HEFF_FP64;
+  const size_t es = f64 ? 8 : 4;
+  if (dpsi) {
+    // E is a symmetric quadratic form: dE/dpsi = 2 H_eff psi
+    HCHECK(launch_apply_prec(*b, prec, psi, dpsi, s));
+    if (f64) HCHECK(launch_scale_f64(static_cast<double*>(dpsi), b->n_elem, 2.0 * gE, s));
+    else HCHECK(launch_scale_f32(static_cast<float*>(dpsi), b->n_elem, (float)(2.0 * gE), s));
+  }
+  void* douts[2] = {dL, dR};
+  for (int side = 0; side < 2; ++side) {
+    void* d = douts[side];
+    if (!d) continue;
+    if (!b->grad[side].ready) make_grad_plan(*b, side, s);
+    const int64_t tot = n[2 * side] + n[2 * side + 1];
+    HCHECK(hipMemsetAsync(d, 0, tot * es, s));
+    if (f64) run_grad<double>(*b, side, ar, psi, d, s);
+    else run_grad<float>(*b, side, ar, psi, d, s);
+    if (f64) HCHECK(launch_scale_f64(static_cast<double*>(d), tot, gE, s));
+    else HCHECK(launch_scale_f32(static_cast<float*>(d), tot, (float)gE, s));
+  }
+  ABI_END(ctx)
+}
+
+extern "C" int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
+                                   const int32_t* pairs, double* g) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!p || !psi || !g || (n_pairs > 0 && !pairs) || n_pairs < 0) throw Error(HEFF_EINVAL, "null argument");
+  Ints I;
+  validate_ints(p, I);
+  const int n = p->n_orb;
+  for (int i = 0; i < n_pairs; ++i) {
+    const int x = pairs[2 * i], y = pairs[2 * i + 1];
+    if (x < 0 || y < 0 || x >= n || y >= n || x == y) throw Error(HEFF_EINVAL, "bad orbital pair");
+  }
+  std::vector<double> dh, dV;
+  for (int i = 0; i < n_pairs; ++i) {
+    rotation_derivative(I, pairs[2 * i], pairs[2 * i + 1], dh, dV);
+    heff_problem q = *p;
+    q.h = dh.data();
+    q.V = dV.data();
+    heff_blocks* bq = nullptr;
+    int rc = heff_build_blocks(ctx, &q, 0u, &bq);
+    if (rc != HEFF_OK) return rc;
+    double e = 0.0;
+    rc = heff_energy(ctx, bq, HEFF_FP64, psi, &e);
+    heff_blocks_free(bq);
+    if (rc != HEFF_OK) return rc;
+    g[i] = e;
+  }
+  ABI_END(ctx)
 }

@@ -140,6 +140,12 @@ hipError_t launch_multidot(const double* A, int64_t lda, int k, const double* x,
 // y[n] = alpha*y[n] + sum_i coef[i] * A[i*lda + n]  (coef on the device)
 hipError_t launch_multiaxpy(const double* A, int64_t lda, int k, const double* coef,
                             double coef_scale, double* y, double alpha, int64_t n, hipStream_t s);
+// out[0] = sum x[n] y[n] in FP64; scratch holds kRedBlocks doubles
+constexpr int kRedBlocks = 512;
+hipError_t launch_dot_f64(const double* x, const double* y, int64_t n, double* out, double* scratch, hipStream_t s);
+hipError_t launch_dot_f32(const float* x, const float* y, int64_t n, double* out, double* scratch, hipStream_t s);
+hipError_t launch_scale_f64(double* x, int64_t n, double a, hipStream_t s);
+hipError_t launch_scale_f32(float* x, int64_t n, float a, hipStream_t s);
 }  // namespace heff
 
 // context object behind the opaque heff_ctx handle of the C ABI

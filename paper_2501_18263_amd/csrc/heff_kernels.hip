@@ -1084,7 +1084,6 @@ hipError_t launch_split_bf16(const double* in, uint16_t* hi, uint16_t* lo, int64
 // ------------------------------------------------------------------ Davidson vector kernels
 // Deterministic two-pass reductions: fixed grid of kRedBlocks partial sums,
 // then one work-group folds them in a fixed order.
-constexpr int kRedBlocks = 512;
 
 __global__ __launch_bounds__(256) void multidot_partial(const double* A, int64_t lda, int k, const double* x,
                                                         int64_t n, double* part) {
@@ -1134,6 +1133,50 @@ __global__ void multiaxpy_kernel(const double* A, int64_t lda, int k, const doub
     for (int i = 0; i < k; ++i) v += cs * coef[i] * A[i * lda + j];
     y[j] = v;
   }
+}
+
+// out = sum_n x[n] y[n] accumulated in FP64 (fixed reduction order)
+template <typename T>
+__global__ __launch_bounds__(256) void dot_partial(const T* x, const T* y, int64_t n, double* part) {
+  __shared__ double sh[256];
+  double v = 0.0;
+  for (int64_t j = blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) v += (double)x[j] * (double)y[j];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+static hipError_t launch_dot_t(const T* x, const T* y, int64_t n, double* out, double* scratch, hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial<T>, dim3(kRedBlocks), dim3(256), 0, s, x, y, n, scratch);
+  hipLaunchKernelGGL(multidot_final, dim3(1), dim3(256), 0, s, scratch, 1, kRedBlocks, out);
+  return hipGetLastError();
+}
+hipError_t launch_dot_f64(const double* x, const double* y, int64_t n, double* out, double* scratch, hipStream_t s) {
+  return launch_dot_t<double>(x, y, n, out, scratch, s);
+}
+hipError_t launch_dot_f32(const float* x, const float* y, int64_t n, double* out, double* scratch, hipStream_t s) {
+  return launch_dot_t<float>(x, y, n, out, scratch, s);
+}
+
+template <typename T>
+__global__ void scale_kernel(T* x, int64_t n, T a) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    x[j] *= a;
+}
+hipError_t launch_scale_f64(double* x, int64_t n, double a, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, x, n, a);
+  return hipGetLastError();
+}
+hipError_t launch_scale_f32(float* x, int64_t n, float a, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, x, n, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_multiaxpy(const double* A, int64_t lda, int k, const double* coef, double coef_scale, double* y,

@@ -74,6 +74,11 @@ _lib.heff_batch_layout.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.P
                                    ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
 _lib.heff_batch_set_grid.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
+_lib.heff_energy.argtypes = [_vp, _vp, _i, _vp, ctypes.POINTER(ctypes.c_double)]
+_lib.heff_energy_backward.argtypes = [_vp, _vp, _i, _vp, ctypes.c_double, _vp, _vp, _vp]
+_lib.heff_op_arena.argtypes = [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_kappa_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
 _lib.heff_batch_io.argtypes = [_vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -85,7 +90,8 @@ _lib.heff_debug_op.restype = ctypes.c_int64
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
-            "heff_task_stats_variant", "heff_task_stats_issued", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_task_stats_variant", "heff_task_stats_issued", "heff_energy", "heff_energy_backward",
+            "heff_op_arena", "heff_kappa_gradient", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
@@ -160,31 +166,44 @@ def _bond_array(tabs, keep):
     return arr
 
 
+def _marshal(p, keep, h=None, V=None):
+    """heff_problem of a synth.Problem; arrays it points to go into `keep`."""
+    from . import synth
+    left = _bond_array(p.left, keep)
+    right = _bond_array(p.right, keep)
+    il = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_left)))()
+    for i in range(len(p.iso_left)):
+        a = np.ascontiguousarray(synth.iso_flat(p.left[i], p.left[i + 1], p.iso_left[i]))
+        keep.append(a)
+        il[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ir = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_right)))()
+    for i in range(len(p.iso_right)):
+        a = np.ascontiguousarray(synth.iso_flat(p.right[i], p.right[i + 1], p.iso_right[i]))
+        keep.append(a)
+        ir[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = np.ascontiguousarray(p.h if h is None else h, dtype=np.float64)
+    V = np.ascontiguousarray(p.V if V is None else V, dtype=np.float64)
+    keep += [h, V, il, ir]
+    return _Problem(p.n_orb, p.n_up, p.n_dn, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), left, right, il, ir)
+
+
+class _DeviceArray:
+    """__cuda_array_interface__ of library-owned device memory, so that torch
+    can view it without a copy."""
+
+    def __init__(self, ptr, n, typestr, owner):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3}
+        self._owner = owner
+
+
 class Blocks:
     """Renormalized operators + task table of one two-site problem."""
 
     def __init__(self, ctx: Context, problem, precs=(FP64,)):
-        from . import synth
         self.ctx = ctx
         keep = []
-        p = problem
-        left = _bond_array(p.left, keep)
-        right = _bond_array(p.right, keep)
-        il = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_left)))()
-        for i in range(len(p.iso_left)):
-            a = np.ascontiguousarray(synth.iso_flat(p.left[i], p.left[i + 1], p.iso_left[i]))
-            keep.append(a)
-            il[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        ir = (ctypes.POINTER(ctypes.c_double) * max(1, len(p.iso_right)))()
-        for i in range(len(p.iso_right)):
-            a = np.ascontiguousarray(synth.iso_flat(p.right[i], p.right[i + 1], p.iso_right[i]))
-            keep.append(a)
-            ir[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        h = np.ascontiguousarray(p.h, dtype=np.float64)
-        V = np.ascontiguousarray(p.V, dtype=np.float64)
-        keep += [h, V]
-        prob = _Problem(p.n_orb, p.n_up, p.n_dn, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                        V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), left, right, il, ir)
+        prob = _marshal(problem, keep)
         mask = 0
         for pr in precs:
             mask |= 1 << pr
@@ -228,6 +247,54 @@ class Blocks:
             self.ctx.check(_lib.heff_task_stats_issued(self._h, v, ctypes.byref(fl), ctypes.byref(ns), ctypes.byref(mx)))
             out.append((fl.value, ns.value, mx.value))
         return out
+
+    def energy(self, psi, prec=FP64):
+        """<psi|H_eff|psi> (psi: device tensor of the precision's dtype)."""
+        self._check_vec(psi, prec)
+        e = ctypes.c_double()
+        self.ctx.check(_lib.heff_energy(self.ctx._h, self._h, prec, _ptr(psi), ctypes.byref(e)))
+        return e.value
+
+    def op_arena(self, prec=FP64):
+        """torch views [left store, left temporaries, right store, right
+        temporaries] of the operand arenas (library memory, no copy)."""
+        import torch
+        ptr = (_vp * 4)()
+        n = (ctypes.c_int64 * 4)()
+        self.ctx.check(_lib.heff_op_arena(self._h, prec, ptr, n))
+        ts = "<f8" if prec == FP64 else "<f4"
+        out = []
+        for i in range(4):
+            if n[i] == 0 or not ptr[i]:
+                out.append(torch.empty(0, dtype=torch.float64 if prec == FP64 else torch.float32, device="cuda"))
+            else:
+                out.append(torch.as_tensor(_DeviceArray(ptr[i], n[i], ts, self), device="cuda"))
+        return out
+
+    def energy_backward(self, psi, gE=1.0, prec=FP64, ops=True):
+        """(dE/dpsi, dE/d[left store | left temps], dE/d[right store | right
+        temps]) scaled by gE; the operand gradients are None if ops is False."""
+        import torch
+        self._check_vec(psi, prec)
+        dt = torch.float64 if prec == FP64 else torch.float32
+        dpsi = torch.empty_like(psi)
+        dL = dR = None
+        if ops:
+            n = (ctypes.c_int64 * 4)()
+            ptr = (_vp * 4)()
+            self.ctx.check(_lib.heff_op_arena(self._h, prec, ptr, n))
+            dL = torch.empty(max(1, n[0] + n[1]), dtype=dt, device="cuda")
+            dR = torch.empty(max(1, n[2] + n[3]), dtype=dt, device="cuda")
+        self.ctx.check(_lib.heff_energy_backward(self.ctx._h, self._h, prec, _ptr(psi), float(gE), _ptr(dpsi),
+                                                 _ptr(dL) if dL is not None else None,
+                                                 _ptr(dR) if dR is not None else None))
+        return dpsi, dL, dR
+
+    def _check_vec(self, psi, prec):
+        import torch
+        want = torch.float64 if prec == FP64 else torch.float32
+        if psi.dtype != want or psi.numel() != self.n_elem or not psi.is_cuda or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous %s device tensor of %d elements" % (want, self.n_elem))
 
     def apply(self, psi, out, prec=FP64):
         """out = H_eff psi (device tensors: float64 for FP64, float32 otherwise)."""
@@ -399,3 +466,60 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def kappa_gradient(ctx: Context, problem, psi, pairs):
+    """Orbital-rotation gradient g_xy = dE/dkappa_xy of E = <psi|H_eff|psi>
+    (psi: float64 device tensor; isometries and psi fixed) for the given
+    orbital pairs; one block build and one product per pair (E is linear in
+    the integrals)."""
+    keep = []
+    prob = _marshal(problem, keep)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    g = np.zeros(len(pr) // 2)
+    ctx.check(_lib.heff_kappa_gradient(ctx._h, ctypes.byref(prob), _ptr(psi), len(pr) // 2,
+                                       pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return g
+
+
+def _energy_function():
+    import torch
+
+    class HeffEnergy(torch.autograd.Function):
+        """E = <psi|H_eff|psi> as a differentiable function of psi and of the
+        four operand arenas (views from Blocks.op_arena, whose memory the
+        product reads).  Usage: HeffEnergy.apply(psi, L0, L1, R0, R1, blocks,
+        prec)."""
+
+        @staticmethod
+        def forward(ctx_, psi, L0, L1, R0, R1, blocks, prec):
+            ctx_.blocks, ctx_.prec = blocks, prec
+            ctx_.sizes = (L0.numel(), L1.numel(), R0.numel(), R1.numel())
+            ctx_.save_for_backward(psi)
+            return torch.tensor(blocks.energy(psi.detach(), prec), dtype=torch.float64, device=psi.device)
+
+        @staticmethod
+        def backward(ctx_, gE):
+            (psi,) = ctx_.saved_tensors
+            need_ops = any(ctx_.needs_input_grad[1:5])
+            dpsi, dL, dR = ctx_.blocks.energy_backward(psi.detach(), float(gE), ctx_.prec, ops=need_ops)
+            n0, n1, n2, n3 = ctx_.sizes
+            gl = [None] * 4
+            if need_ops:
+                gl = [dL[:n0], dL[n0:n0 + n1], dR[:n2], dR[n2:n2 + n3]]
+            return (dpsi, gl[0], gl[1], gl[2], gl[3], None, None)
+
+    return HeffEnergy
+
+
+_HE = None
+
+
+def heff_energy_function():
+    """The torch.autograd.Function of E = <psi|H_eff|psi> (created lazily so
+    that importing this module does not import torch)."""
+    global _HE
+    if _HE is None:
+        _HE = _energy_function()
+    return _HE

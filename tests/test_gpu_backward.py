@@ -1,0 +1,152 @@
+"""GPU backward of E = <psi|H_eff|psi>: psi gradient against the oracle's
+2 H_eff psi, operand-arena gradients against exact finite differences (E is
+linear in every single arena entry), FP32 against FP64, the autograd
+function, and the orbital-rotation gradient against the oracle (N=6, full
+two-site space) and against central differences of rotated-integral
+energies (N=16, D=256)."""
+import numpy as np
+import pytest
+
+from paper_2501_18263_amd import synth
+from oracle import block, grad
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def heff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2501_18263_amd import heff as H
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(heff):
+    return heff.Context(0)
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.tensor(x, dtype=dtype, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def case8(heff, ctx):
+    p = synth.make_problem(8, 32, 5)
+    B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32))
+    psi = synth.random_psi(p)
+    return p, B, psi
+
+
+def test_energy_and_psi_gradient_match_oracle(heff, case8):
+    p, B, psi = case8
+    print("case backward psi N=8 D=32 seed=5", flush=True)
+    hp = block.heff_apply(p, psi)
+    e0 = float(psi @ hp)
+    x = _dev(psi)
+    e = B.energy(x)
+    assert abs(e - e0) <= 1e-11 * abs(e0)
+    dpsi, _, _ = B.energy_backward(x, gE=1.0, ops=False)
+    d = dpsi.cpu().numpy()
+    assert np.linalg.norm(d - 2 * hp) <= 1e-10 * np.linalg.norm(2 * hp)
+    # Euler: E is homogeneous of degree two in psi
+    assert abs(float(d @ psi) - 2 * e0) <= 1e-10 * abs(e0)
+    # the upstream gradient scales the result
+    d3, _, _ = B.energy_backward(x, gE=-0.5, ops=False)
+    assert np.allclose(d3.cpu().numpy(), -0.5 * d, rtol=0, atol=1e-14 * np.abs(d).max())
+
+
+def test_operand_gradients_are_exact_derivatives(heff, case8):
+    p, B, psi = case8
+    print("case backward operands N=8 D=32 seed=5", flush=True)
+    x = _dev(psi)
+    _, dL, dR = B.energy_backward(x)
+    views = B.op_arena(heff.FP64)
+    n = [v.numel() for v in views]
+    grads = [dL[:n[0]], dL[n[0]:n[0] + n[1]], dR[:n[2]], dR[n[2]:n[2] + n[3]]]
+    rng = np.random.default_rng(11)
+    e0 = B.energy(x)
+    checked = 0
+    for v, gv in zip(views, grads):
+        if v.numel() == 0:
+            continue
+        g = gv.cpu().numpy()
+        nz = np.nonzero(g)[0]
+        pick = list(rng.choice(nz, min(6, len(nz)), replace=False)) if len(nz) else []
+        pick += list(rng.choice(v.numel(), 2, replace=False))
+        for i in pick:
+            i = int(i)
+            old = float(v[i].item())
+            v[i] = old + 1.0
+            e1 = B.energy(x)
+            v[i] = old
+            # E is linear in one arena entry: the unit step is exact
+            assert abs((e1 - e0) - g[i]) <= 1e-10 * max(1.0, abs(e0)), (i, e1 - e0, g[i])
+            checked += 1
+    assert B.energy(x) == e0
+    assert checked >= 16
+
+
+def test_fp32_gradients_track_fp64(heff, case8):
+    p, B, psi = case8
+    print("case backward fp32 N=8 D=32 seed=5", flush=True)
+    d64, L64, R64 = B.energy_backward(_dev(psi))
+    d32, L32, R32 = B.energy_backward(_dev(psi, torch.float32), prec=heff.FP32)
+    for a, b in ((d64, d32), (L64, L32), (R64, R32)):
+        a = a.cpu().numpy()
+        b = b.double().cpu().numpy()
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(a)
+
+
+def test_autograd_function(heff, case8):
+    p, B, psi = case8
+    print("case backward autograd N=8 D=32 seed=5", flush=True)
+    HE = heff.heff_energy_function()
+    x = _dev(psi).requires_grad_(True)
+    # views of the library's arenas, which the product reads
+    ops = [v.requires_grad_(True) for v in B.op_arena(heff.FP64)]
+    E = HE.apply(x, *ops, B, heff.FP64)
+    (2.0 * E).backward()
+    d, dL, dR = B.energy_backward(_dev(psi), gE=2.0)
+    assert torch.equal(x.grad, d)
+    n = [o.numel() for o in ops]
+    assert torch.equal(ops[0].grad, dL[:n[0]])
+    assert torch.equal(ops[3].grad, dR[n[2]:n[2] + n[3]])
+
+
+def test_kappa_gradient_matches_oracle(heff, ctx):
+    # N=6 with every sector kept: Phi = P psi spans the whole Fock sector
+    p = synth.make_problem(6, 400, 5)
+    print("case kappa N=6 full seed=5", flush=True)
+    psi = np.random.default_rng(7).standard_normal(synth.psi_size(p))
+    pairs = [(x, y) for x in range(6) for y in range(x + 1, 6)]
+    g = heff.kappa_gradient(ctx, p, _dev(psi), pairs)
+    ref = grad.kappa_gradient(p, psi, pairs)
+    assert np.abs(g - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_kappa_gradient_central_differences_n16(heff, ctx):
+    p = synth.make_problem(16, 256, 5)
+    print("case kappa N=16 D=256 seed=5", flush=True)
+    psi = synth.random_psi(p)
+    x = _dev(psi)
+    pairs = [(0, 1), (3, 9), (7, 8)]
+    g = heff.kappa_gradient(ctx, p, x, pairs)
+    eps = 1e-5
+    import scipy.linalg as sla
+    for (a, b), gab in zip(pairs, g):
+        K = grad.generator(16, a, b)
+        es = []
+        for sgn in (1.0, -1.0):
+            h2, V2 = grad.rotate(p.h, p.V, sla.expm(sgn * eps * K))
+            V2 = 0.125 * (V2 + V2.transpose(1, 0, 2, 3) + V2.transpose(0, 1, 3, 2) + V2.transpose(1, 0, 3, 2)
+                          + V2.transpose(2, 3, 0, 1) + V2.transpose(3, 2, 0, 1) + V2.transpose(2, 3, 1, 0)
+                          + V2.transpose(3, 2, 1, 0))
+            q = synth.make_problem(16, 256, 5, h=0.5 * (h2 + h2.T), V=V2)
+            Bq = heff.Blocks(ctx, q)
+            es.append(Bq.energy(x))
+            Bq.close()
+        fd = (es[0] - es[1]) / (2 * eps)
+        assert abs(fd - gab) <= 1e-7, (a, b, fd, gab)
