@@ -144,8 +144,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the product shards by terms with one "
-              "all-reduce per product; see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: the two-site product runs on one GPU only (a multi-GPU split would shard "
+              "the task table by output blocks); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":

@@ -94,7 +94,8 @@ const char* heff_last_error(const heff_ctx* ctx);
  * isometries), the complementary-operator sums and the task table of the
  * two-site product (Sec. II.C).  All inputs are host memory read during
  * the call.  prec_mask: bit (1 << HEFF_FP32) and/or (1 << HEFF_BF16X3)
- * also prepare the reduced-precision operand copies.  Validates symmetry
+ * also prepare the FP32 operand copies that both reduced-precision products
+ * read (the split-bf16 product splits FP32 values into hi/lo on the fly).  Validates symmetry
  * of h and V (1e-12), sorted non-empty bond tables consistent with the
  * isometry shapes and orthonormal isometry columns (1e-10).  Synchronizes
  * the context stream.  *out is owned by the caller (heff_blocks_free). */
@@ -114,10 +115,10 @@ int heff_psi_layout(const heff_blocks* b, int64_t* n_elem, int32_t* n_blk,
  * block read once + Psi read + Psi' written). bytes may be NULL. */
 int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* flops, double* bytes3);
 
-/* Kernel timing of heff_apply (SURVEY-style per-phase timers): when enabled,
+/* Kernel timing of heff_apply (per-phase timers): when enabled,
  * every product launch records HIP events on the context stream around each
  * of its kernel-variant launches (variants 0..3 handle output blocks whose
- * largest dimension is <= 32, 64, 128, 256).  heff_timing() enables (1) or
+ * width and task middle dimensions are <= 32, 64, 128, 256).  heff_timing() enables (1) or
  * disables (0) recording and clears what was recorded; heff_timing_read()
  * synchronizes the stream, writes per variant the summed milliseconds
  * ms[4] and the number of recorded launches launches[4] since the last

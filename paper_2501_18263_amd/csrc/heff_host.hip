@@ -484,24 +484,20 @@ static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
   tasks.swap(nk);
 }
 
-// Largest dimension a tile's kernels hold in registers: e and c for the
-// FP64/FP32 kernels, also b for the bf16 kernel (with_b).
-static int tile_dim(const Tile& t, const std::vector<Task>& tasks, bool with_b = false) {
+// Largest dimension a tile's kernels hold in registers: the output width e
+// and the middle dimension c of its tasks (T = op(L) op(X) has c columns).
+static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
   int d = t.e;
-  for (int k = t.t0; k < t.t1; ++k) {
-    d = std::max<int>(d, tasks[k].c);
-    if (with_b && !(tasks[k].flags & (T_IDL | T_IDX))) d = std::max<int>(d, tasks[k].b);
-  }
+  for (int k = t.t0; k < t.t1; ++k) d = std::max<int>(d, tasks[k].c);
   return d;
 }
 
 // Work items of the matrix-core kernels, one list per variant (tiles taken
 // in the given order, each cut into kTileRows-row items).
 static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
-                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants],
-                       bool with_b = false) {
+                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants]) {
   for (int t : order) {
-    int v = variant_of(tile_dim(tiles[t], tasks, with_b));
+    int v = variant_of(tile_dim(tiles[t], tasks));
     for (int r = 0; r < tiles[t].a; r += kTileRows) lists[v].push_back({t, r});
   }
 }
@@ -927,18 +923,19 @@ struct heff_blocks {
   std::map<std::array<int, 3>, int> blk_index;  // (qa index, s_k, s_k1) -> block
   int64_t n_elem = 0;
   // product task table
-  heff::DevBuf d_tiles, d_tasks, d_work, d_dtiles, d_dtasks;
+  heff::DevBuf d_tiles, d_tasks, d_dtiles, d_dtasks;
   heff::DevWorkSet mwork;  // matrix-core work lists
   std::vector<heff::Tile> h_tiles;  // host copies (used to assemble batches)
   std::vector<heff::Task> h_tasks;
-  int64_t n_tiles = 0, n_tasks = 0, n_work = 0, n_dtasks = 0;
+  int64_t n_tiles = 0, n_tasks = 0, n_dtasks = 0;
   double flops = 0.0, bytes[3] = {0, 0, 0};
   double vflops[heff::kNumVariants] = {0, 0, 0, 0};  // algorithmic flops per kernel variant
   double vissued[heff::kNumVariants] = {0, 0, 0, 0};  // matrix-instruction flops of the FP64/FP32 kernel
   int64_t vsteps[heff::kNumVariants] = {0, 0, 0, 0};  // pipeline steps summed over work-groups
   int64_t vmaxsteps[heff::kNumVariants] = {0, 0, 0, 0};  // pipeline steps of the longest work-group
-  // reduced-precision operand copies: [L store, L temps, R store, R temps]
-  heff::DevBuf f32[4], bhi[4], blo[4];
+  // FP32 operand copies (FP32 and split-bf16 products): [L store, L temps,
+  // R store, R temps]
+  heff::DevBuf f32[4];
   // backward: task tables of the operand gradients (0: left, 1: right
   // operator arenas), built on first use; scratch of heff_energy
   struct GradPlan {
@@ -1231,7 +1228,6 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   std::vector<Tile> tiles(nb), dtiles(nb);
   std::vector<Task> tasks;
   std::vector<DiagTask> dtasks;
-  std::vector<Work> work;
   for (int y = 0; y < nb; ++y) {
     Tile t{};
     t.offOut = B.blk_off[y];
@@ -1257,15 +1253,13 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
     for (int k = tiles[b].t0; k < tiles[b].t1; ++k) wb += task_flops(tasks[k]) / std::max(1, tiles[b].a);
     return wa > wb;
   });
-  for (int y : order)
-    for (int r = 0; r < tiles[y].a; r += kPlainRows) work.push_back({y, r});
   std::vector<Work> lists[kNumVariants];
-  split_work(tiles, tasks, order, lists, true);
+  split_work(tiles, tasks, order, lists);
   B.mwork.upload_lists(lists, s);
   for (int y = 0; y < nb; ++y) {
     double fl = 0.0;
     for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
-    const int v = variant_of(tile_dim(tiles[y], tasks, true));
+    const int v = variant_of(tile_dim(tiles[y], tasks));
     B.vflops[v] += fl;
     // what the FP64/FP32 kernel issues: per active 16-row wave, 4 ceil(c/16)
     // MFMAs per stage-1 step (ceil(b/16) steps) and 4 ceil(e/16) per stage-2
@@ -1284,7 +1278,6 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
   B.n_tiles = nb;
   B.n_tasks = (int64_t)tasks.size();
-  B.n_work = (int64_t)work.size();
   B.n_dtasks = (int64_t)dtasks.size();
   double psi_elems = (double)B.n_elem;
   B.bytes[0] = 8.0 * (op_elems + 2 * psi_elems);
@@ -1294,7 +1287,6 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   upload(B.d_tasks, tasks, s);
   B.h_tiles = tiles;
   B.h_tasks = tasks;
-  upload(B.d_work, work, s);
   upload(B.d_dtiles, dtiles, s);
   upload(B.d_dtasks, dtasks, s);
   HCHECK(hipStreamSynchronize(s));
@@ -1343,6 +1335,33 @@ using namespace heff;
   }                                                                 \
   return HEFF_OK;
 
+namespace heff {
+// Streams of the product's kernel variants, forked from the context stream
+// (so the variants run concurrently: the small-block variants are bound by
+// their longest work item and fill the chip while the large one runs) and
+// joined back into it.  All default priority.
+static void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
+  if (!c->fork) {
+    HCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    for (int v = 0; v < kNumVariants; ++v) {
+      HCHECK(hipStreamCreateWithFlags(&c->vs[v], hipStreamNonBlocking));
+      HCHECK(hipEventCreateWithFlags(&c->join[v], hipEventDisableTiming));
+    }
+  }
+  HCHECK(hipEventRecord(c->fork, c->stream));
+  for (int v = 0; v < kNumVariants; ++v) {
+    HCHECK(hipStreamWaitEvent(c->vs[v], c->fork, 0));
+    out[v] = c->vs[v];
+  }
+}
+static void join_variants(heff_ctx* c) {
+  for (int v = 0; v < kNumVariants; ++v) {
+    HCHECK(hipEventRecord(c->join[v], c->vs[v]));
+    HCHECK(hipStreamWaitEvent(c->stream, c->join[v], 0));
+  }
+}
+}  // namespace heff
+
 extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
   if (!out) return HEFF_EINVAL;
   *out = nullptr;
@@ -1359,11 +1378,16 @@ extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
 
 extern "C" int heff_destroy(heff_ctx* c) {
   if (c) {
+    (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (int v = 0; v < kNumVariants; ++v) {
+      if (c->vs[v]) (void)hipStreamSynchronize(c->vs[v]);
       for (hipEvent_t e : c->ev_start[v]) (void)hipEventDestroy(e);
       for (hipEvent_t e : c->ev_stop[v]) (void)hipEventDestroy(e);
+      if (c->vs[v]) (void)hipStreamDestroy(c->vs[v]);
+      if (c->join[v]) (void)hipEventDestroy(c->join[v]);
     }
+    if (c->fork) (void)hipEventDestroy(c->fork);
   }
   delete c;
   return HEFF_OK;
@@ -1430,15 +1454,10 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
   const double* srcs[4] = {B->L->store.dev.as<double>(), B->Ltmp.tmp.dev.as<double>(),
                            B->R->store.dev.as<double>(), B->Rtmp.tmp.dev.as<double>()};
   int64_t sizes[4] = {B->L->store.total, B->Ltmp.tmp.total, B->R->store.total, B->Rtmp.tmp.total};
-  for (int i = 0; i < 4; ++i) {
-    if (prec_mask & (1u << HEFF_FP32)) {
+  if (prec_mask & ((1u << HEFF_FP32) | (1u << HEFF_BF16X3))) {
+    for (int i = 0; i < 4; ++i) {
       B->f32[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * sizeof(float));
       if (sizes[i]) HCHECK(launch_convert_f32(srcs[i], B->f32[i].as<float>(), sizes[i], s));
-    }
-    if (prec_mask & (1u << HEFF_BF16X3)) {
-      B->bhi[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * 2);
-      B->blo[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * 2);
-      if (sizes[i]) HCHECK(launch_split_bf16(srcs[i], B->bhi[i].as<uint16_t>(), B->blo[i].as<uint16_t>(), sizes[i], s));
     }
   }
   HCHECK(hipStreamSynchronize(s));
@@ -1480,7 +1499,6 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
   HCHECK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const Tile* tl = b->d_tiles.as<Tile>();
-  const Work* wk = b->d_work.as<Work>();
   const Task* tk = b->d_tasks.as<Task>();
   hipEvent_t evbuf[kNumVariants][2] = {};
   hipEvent_t(*ev)[2] = nullptr;
@@ -1502,7 +1520,10 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     bs.R[1] = b->Rtmp.tmp.dev.as<double>();
     bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
     bs.out = static_cast<double*>(out);
-    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, s, ev));
+    hipStream_t vs[kNumVariants];
+    fork_variants(ctx, vs);
+    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, vs, ev));
+    join_variants(ctx);
   } else if (prec == HEFF_FP32) {
     if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
     Bases<float> bs{};
@@ -1512,15 +1533,23 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     bs.R[1] = b->f32[3].as<float>();
     bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
     bs.out = static_cast<float*>(out);
-    HCHECK(launch_mfma_f32(tl, b->mwork.ws, tk, bs, s, ev));
+    hipStream_t vs[kNumVariants];
+    fork_variants(ctx, vs);
+    HCHECK(launch_mfma_f32(tl, b->mwork.ws, tk, bs, vs, ev));
+    join_variants(ctx);
   } else if (prec == HEFF_BF16X3) {
     if (!(b->prec_mask & (1u << HEFF_BF16X3))) throw Error(HEFF_ENOTSUP, "BF16X3 operands were not built");
-    const uint16_t* Lhi[2] = {b->bhi[0].as<uint16_t>(), b->bhi[1].as<uint16_t>()};
-    const uint16_t* Llo[2] = {b->blo[0].as<uint16_t>(), b->blo[1].as<uint16_t>()};
-    const uint16_t* Rhi[2] = {b->bhi[2].as<uint16_t>(), b->bhi[3].as<uint16_t>()};
-    const uint16_t* Rlo[2] = {b->blo[2].as<uint16_t>(), b->blo[3].as<uint16_t>()};
-    HCHECK(launch_bf16x3_mfma(tl, b->mwork.ws, tk, Lhi, Llo, Rhi, Rlo, static_cast<const float*>(psi),
-                              static_cast<float*>(out), s, ev));
+    Bases<float> bs{};
+    bs.L[0] = b->f32[0].as<float>();
+    bs.L[1] = b->f32[1].as<float>();
+    bs.R[0] = b->f32[2].as<float>();
+    bs.R[1] = b->f32[3].as<float>();
+    bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
+    bs.out = static_cast<float*>(out);
+    hipStream_t vs[kNumVariants];
+    fork_variants(ctx, vs);
+    HCHECK(launch_bf16x3(tl, b->mwork.ws, tk, bs, vs, ev));
+    join_variants(ctx);
   } else {
     throw Error(HEFF_EINVAL, "unknown precision");
   }
@@ -2152,29 +2181,6 @@ static void run_grad(const heff_blocks& B, int side, void* const ar[4], const vo
     HCHECK(launch_mfma_f32(G.tiles.as<Tile>(), G.work.ws, G.tasks.as<Task>(), bs, s));
 }
 
-static hipError_t launch_apply_prec(const heff_blocks& B, int prec, const void* psi, void* out, hipStream_t s) {
-  void* ar[4];
-  int64_t n[4];
-  arenas(B, prec, ar, n);
-  if (prec == HEFF_FP64) {
-    Bases<double> bs{};
-    for (int i = 0; i < 2; ++i) {
-      bs.L[i] = static_cast<const double*>(ar[i]);
-      bs.R[i] = static_cast<const double*>(ar[2 + i]);
-    }
-    bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
-    bs.out = static_cast<double*>(out);
-    return launch_mfma_f64(B.d_tiles.as<Tile>(), B.mwork.ws, B.d_tasks.as<Task>(), bs, s);
-  }
-  Bases<float> bs{};
-  for (int i = 0; i < 2; ++i) {
-    bs.L[i] = static_cast<const float*>(ar[i]);
-    bs.R[i] = static_cast<const float*>(ar[2 + i]);
-  }
-  bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
-  bs.out = static_cast<float*>(out);
-  return launch_mfma_f32(B.d_tiles.as<Tile>(), B.mwork.ws, B.d_tasks.as<Task>(), bs, s);
-}
 
 // first-order change of the integrals under the orbital rotation generated
 // by K = E_xy - E_yx: dh = K^T h + h K, dV_ijkl = sum over the four index
@@ -2229,7 +2235,7 @@ extern "C" int heff_energy(heff_ctx* ctx, const heff_blocks* b, int prec, const 
   char* base = b->escratch.as<char>();
   void* hp = base;
   double* red = reinterpret_cast<double*>(base + hbytes);
-  HCHECK(launch_apply_prec(*b, prec, psi, hp, s));
+  if (int rc = heff_apply(ctx, b, prec, psi, hp)) throw Error(rc, ctx->err);
   if (prec == HEFF_FP64)
     HCHECK(launch_dot_f64(static_cast<const double*>(psi), static_cast<const double*>(hp), b->n_elem, red + kRedBlocks,
                           red, s));
@@ -2257,7 +2263,7 @@ extern "C" int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int pre
   const size_t es = f64 ? 8 : 4;
   if (dpsi) {
     // E is a symmetric quadratic form: dE/dpsi = 2 H_eff psi
-    HCHECK(launch_apply_prec(*b, prec, psi, dpsi, s));
+    if (int rc = heff_apply(ctx, b, prec, psi, dpsi)) throw Error(rc, ctx->err);
     if (f64) HCHECK(launch_scale_f64(static_cast<double*>(dpsi), b->n_elem, 2.0 * gE, s));
     else HCHECK(launch_scale_f32(static_cast<float*>(dpsi), b->n_elem, (float)(2.0 * gE), s));
   }

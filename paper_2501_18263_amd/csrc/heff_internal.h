@@ -8,7 +8,6 @@
 namespace heff {
 
 // rows of one output block handled by one work item of the plain kernel
-constexpr int kPlainRows = 16;
 // largest output width and inner dimension one task may have in the
 // matrix-core kernels (larger blocks are split into several tasks / tiles)
 constexpr int kMaxDim = 256;
@@ -93,20 +92,28 @@ struct WorkSet {
 
 // ---- launchers (heff_kernels.hip) ----
 // ev: optional [kNumVariants][2] start/stop events recorded around each launch
-hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b, hipStream_t s,
-                           hipEvent_t (*ev)[2] = nullptr);
-hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b, hipStream_t s,
-                           hipEvent_t (*ev)[2] = nullptr);
-hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                               const uint16_t* Lhi[2], const uint16_t* Llo[2],
-                               const uint16_t* Rhi[2], const uint16_t* Rlo[2],
-                               const float* X, float* out, hipStream_t s);
+// s[v]: stream of variant v (the variants touch disjoint outputs and may run
+// concurrently); the single-stream forms launch all variants on one stream
+hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
+                           const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
+hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
+                           const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
+inline hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
+                                  hipStream_t s, hipEvent_t (*ev)[2] = nullptr) {
+  const hipStream_t a[kNumVariants] = {s, s, s, s};
+  return launch_mfma_f64(tiles, ws, tasks, b, a, ev);
+}
+inline hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
+                                  hipStream_t s, hipEvent_t (*ev)[2] = nullptr) {
+  const hipStream_t a[kNumVariants] = {s, s, s, s};
+  return launch_mfma_f32(tiles, ws, tasks, b, a, ev);
+}
 // grid[v]: persistent work-groups of variant v
 hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, const ProbBases<float>* pb,
                                  const float* X, float* out, const int grid[kNumVariants], hipStream_t s);
-hipError_t launch_bf16x3_mfma(const Tile* tiles, const WorkSet& ws, const Task* tasks, const uint16_t* Lhi[2],
-                              const uint16_t* Llo[2], const uint16_t* Rhi[2], const uint16_t* Rlo[2], const float* X,
-                              float* out, hipStream_t s, hipEvent_t (*ev)[2] = nullptr);
+// split-precision (bf16 hi+lo, FP32 accumulation) product on the FP32 operand arenas
+hipError_t launch_bf16x3(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
+                         const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
 // symmetric eigenproblems of the truncation (one work-group each, n <= kMaxEig)
 constexpr int kMaxEig = 1024;
 struct EigJob {
@@ -128,8 +135,6 @@ hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks
 hipError_t launch_gemm_f64(int64_t m, int64_t n, int64_t k, const double* A, const double* B,
                            double* C, hipStream_t s);
 hipError_t launch_convert_f32(const double* in, float* out, int64_t n, hipStream_t s);
-hipError_t launch_split_bf16(const double* in, uint16_t* hi, uint16_t* lo, int64_t n,
-                             hipStream_t s);
 hipError_t launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
 
@@ -153,7 +158,11 @@ struct heff_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
-  // per-variant kernel timing of the product (HIP events on `stream`)
+  // per-variant kernel timing of the product (HIP events on the variant's stream)
   bool timing = false;
   std::vector<hipEvent_t> ev_start[heff::kNumVariants], ev_stop[heff::kNumVariants];
+  // streams of the product's kernel variants (default priority, forked from
+  // and joined back into `stream` by events); created on first use
+  hipStream_t vs[heff::kNumVariants] = {};
+  hipEvent_t fork = nullptr, join[heff::kNumVariants] = {};
 };

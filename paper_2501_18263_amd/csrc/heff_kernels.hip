@@ -29,19 +29,6 @@ __device__ __forceinline__ const T* pick(bool c, const T* a, const T* b) {
   return (const T*)(x ^ ((x ^ y) & m));
 }
 
-// round-to-nearest-even float -> bf16 bits
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-constexpr int kThreads = 256;
-constexpr int kAcc = kPlainRows * kMaxDim / kThreads;
-
 // ------------------------------------------------------------------ chained product (MFMA)
 // Matrix-core version: one work-group = 4 waves = 64 rows of one output
 // block; wave w owns rows [16w, 16w+16).  A task  f op(L) op(X) op(R)  is
@@ -489,10 +476,11 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 
 template <typename T>
 static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<T> b,
-                                       hipStream_t s, hipEvent_t (*ev)[2]) {
+                                       const hipStream_t* ss, hipEvent_t (*ev)[2]) {
   // largest blocks first: their work items are the longest
   for (int v = kNumVariants - 1; v >= 0; --v) {
     if (ws.n[v] <= 0) continue;
+    hipStream_t s = ss[v];
     if (ev && ev[v][0]) {
       hipError_t e = hipEventRecord(ev[v][0], s);
       if (e != hipSuccess) return e;
@@ -514,305 +502,272 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
   return hipSuccess;
 }
 
-hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b, hipStream_t s,
-                           hipEvent_t (*ev)[2]) {
+hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
+                           const hipStream_t* s, hipEvent_t (*ev)[2]) {
   return launch_mfma_variants<double>(tiles, ws, tasks, b, s, ev);
 }
-hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b, hipStream_t s,
-                           hipEvent_t (*ev)[2]) {
+hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
+                           const hipStream_t* s, hipEvent_t (*ev)[2]) {
   return launch_mfma_variants<float>(tiles, ws, tasks, b, s, ev);
 }
 
 // ------------------------------------------------------------------ chained product, bf16 split
-// Products of split operands: a*b ~= ah*bh + ah*bl + al*bh with FP32
-// accumulation; Psi and the intermediate T are split on the fly
-// (hi = RNE_bf16(x), lo = RNE_bf16(x - hi)).
-struct Bf16Args {
-  const uint16_t* Lhi[2];
-  const uint16_t* Llo[2];
-  const uint16_t* Rhi[2];
-  const uint16_t* Rlo[2];
-  const float* X;
-  float* out;
+// Split precision: every FP32 operand value x is written to LDS as
+// hi = RNE_bf16(x) and lo = RNE_bf16(x - hi), and each product a b is
+// formed as ah bh + ah bl + al bh on v_mfma_f32_16x16x16_bf16 with FP32
+// accumulation (the lo*lo term, of relative size 2^-16, is dropped).  The
+// step pipeline, cursors and global loads are those of the FP32 kernel
+// (same FP32 operand arenas); the LDS slices hold the split values with k
+// contiguous per row or column, so that a lane's four operand values of
+// k = 4g..4g+3 are one 8-byte read:
+//   op(X) slice  [m][k]  (16 k per column m),
+//   op(R) slice  [col][j],
+//   op(L) slice  [row][k].
+// Stage 1 result layout: register r of lane (g, n) holds
+// T[row n][16 cc + 4g + r], which is directly the A operand of stage 2 for
+// k = 4g + r of the c-slice (split into hi/lo in registers).
+typedef short b3v4 __attribute__((ext_vector_type(4)));
+typedef float f32v4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float bf_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <int NT>
+struct B3Smem {
+  static constexpr int W = 16 * NT;
+  static constexpr int KP = 20;  // 16 values + 4 padding (rows stay 8-byte aligned)
+  uint16_t sh[2][W * KP], sl[2][W * KP];
+  uint16_t lh[2][64 * KP], ll[2][64 * KP];
 };
 
-__device__ __forceinline__ float mul3(float ah, float al, float bh, float bl) { return ah * bh + (ah * bl + al * bh); }
+__device__ __forceinline__ void put_split(uint16_t* hi, uint16_t* lo, int pos, float v) {
+  const uint16_t h = bf_bits(v);
+  hi[pos] = h;
+  lo[pos] = bf_bits(v - bf_val(h));
+}
 
-__global__ __launch_bounds__(kThreads) void chain_bf16x3_plain(const Tile* __restrict__ tiles,
-                                                               const Work* __restrict__ work,
-                                                               const Task* __restrict__ tasks, Bf16Args B) {
-  __shared__ float Ts[kPlainRows * (kMaxDim + 1)];
-  const Work w = work[blockIdx.x];
-  const Tile tile = tiles[w.tile];
-  const int rows = min(kPlainRows, tile.a - w.row0);
-  const int E = tile.e;
+template <int NT, int P>
+__device__ __forceinline__ void store_step_b3(const Task& t, const Cursor& cu, const Lane<16 * NT>& ln, int row0,
+                                              const Stage<float, NT>& st, B3Smem<NT>& sm) {
+  constexpr int W = 16 * NT, KQ = 256 / W, KP = B3Smem<NT>::KP;
+  const uint32_t fl = t.flags;
+  const int base = 16 * cu.s;
+  uint16_t* hi = sm.sh[P];
+  uint16_t* lo = sm.sl[P];
+  if (cu.ph == 0) {
+    const int klim = t.b - base;
+    if (fl & T_IDX) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int kk = ln.tW + KQ * q;
+        put_split(hi, lo, ln.tm * KP + kk, base + kk == ln.tm ? 1.f : 0.f);
+      }
+    } else if (fl & T_TX) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) put_split(hi, lo, (ln.t4 + 16 * q) * KP + ln.t15, st.v[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) put_split(hi, lo, ln.tm * KP + ln.tW + KQ * q, st.v[q]);
+    }
+    const float f = (float)t.f;
+    if (fl & T_IDL) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = ln.t4 + 16 * q;
+        put_split(sm.lh[P], sm.ll[P], r * KP + ln.t15, (row0 + r == base + ln.t15) ? f : 0.f);
+      }
+    } else if (fl & T_TL) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = ln.t6 + 4 * q;
+        put_split(sm.lh[P], sm.ll[P], ln.t63 * KP + kk, kk < klim ? st.l[q] * f : 0.f);
+      }
+    } else {
+      const bool ok = ln.t15 < klim;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        put_split(sm.lh[P], sm.ll[P], (ln.t4 + 16 * q) * KP + ln.t15, ok ? st.l[q] * f : 0.f);
+    }
+  } else {
+    const int jlim = t.c - base;
+    if (fl & T_IDR) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int j = ln.tW + KQ * q;
+        put_split(hi, lo, ln.tm * KP + j, base + j == ln.tm ? 1.f : 0.f);
+      }
+    } else if (fl & T_TR) {
+      const bool ok = ln.t15 < jlim;
+#pragma unroll
+      for (int q = 0; q < NT; ++q) put_split(hi, lo, (ln.t4 + 16 * q) * KP + ln.t15, ok ? st.v[q] : 0.f);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int j = ln.tW + KQ * q;
+        put_split(hi, lo, ln.tm * KP + j, j < jlim ? st.v[q] : 0.f);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ f32v4 mfma_b3(b3v4 ah, b3v4 al, b3v4 bh, b3v4 bl, f32v4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+}
+__device__ __forceinline__ b3v4 ld4(const uint16_t* p) { return *reinterpret_cast<const b3v4*>(p); }
+
+template <int NT, int NC, int P>
+__device__ __forceinline__ void stage1_b3(f32v4 (&Tc)[NT], const B3Smem<NT>& sm, int wave, int g, int n) {
+  constexpr int KP = B3Smem<NT>::KP;
+  const int lo = (wave * 16 + n) * KP + 4 * g;
+  const b3v4 bh = ld4(sm.lh[P] + lo), bl = ld4(sm.ll[P] + lo);
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    const int xo = (cc * 16 + n) * KP + 4 * g;
+    Tc[cc] = mfma_b3(ld4(sm.sh[P] + xo), ld4(sm.sl[P] + xo), bh, bl, Tc[cc]);
+  }
+}
+template <int NT, int NE, int CC, int P>
+__device__ __forceinline__ void stage2_b3(f32v4 (&acc)[NT], const f32v4 (&Tc)[NT], const B3Smem<NT>& sm, int g, int n) {
+  constexpr int KP = B3Smem<NT>::KP;
+  b3v4 th, tl;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint16_t h = bf_bits(Tc[CC][r]);
+    th[r] = (short)h;
+    tl[r] = (short)bf_bits(Tc[CC][r] - bf_val(h));
+  }
+#pragma unroll
+  for (int nt = 0; nt < NE; ++nt) {
+    const int ro = (nt * 16 + n) * KP + 4 * g;
+    acc[nt] = mfma_b3(th, tl, ld4(sm.sh[P] + ro), ld4(sm.sl[P] + ro), acc[nt]);
+  }
+}
+template <int NT, int NC, int P>
+__device__ __forceinline__ void stage1_b3_sw(int nc, f32v4 (&Tc)[NT], const B3Smem<NT>& sm, int wave, int g, int n) {
+  if constexpr (NC < NT) {
+    if (nc > NC) {
+      stage1_b3_sw<NT, NC + 1, P>(nc, Tc, sm, wave, g, n);
+      return;
+    }
+  }
+  stage1_b3<NT, NC, P>(Tc, sm, wave, g, n);
+}
+template <int NT, int NE, int CC, int P>
+__device__ __forceinline__ void stage2_b3_sw(int s, f32v4 (&acc)[NT], const f32v4 (&Tc)[NT], const B3Smem<NT>& sm,
+                                             int g, int n) {
+  if constexpr (CC + 1 < NT) {
+    if (s > CC) {
+      stage2_b3_sw<NT, NE, CC + 1, P>(s, acc, Tc, sm, g, n);
+      return;
+    }
+  }
+  stage2_b3<NT, NE, CC, P>(acc, Tc, sm, g, n);
+}
+
+template <int NT, int NE, int P>
+__device__ __forceinline__ void pipe_step_b3(const Tile& tile, const Task* __restrict__ tasks, const Bases<float>& B,
+                                             B3Smem<NT>& sm, const Lane<16 * NT>& ln, int row0, bool wave_on, int wave,
+                                             int g, int n, f32v4 (&Tc)[NT], f32v4 (&acc)[NT], bool& live, Cursor& c0,
+                                             Task& t0, Task& pre) {
+  Cursor c1 = c0;
+  Task t1 = t0;
+  const bool more = next_step(c1, t1, pre, tasks, tile.t1);
+  Stage<float, NT> st;
+  if (more) st = load_step<float, NT>(t1, B, c1, ln, row0);
+  if (wave_on) {
+    if (c0.ph == 0) {
+      if (c0.s == 0) {
+#pragma unroll
+        for (int cc = 0; cc < NT; ++cc) Tc[cc] = f32v4{0, 0, 0, 0};
+      }
+      stage1_b3_sw<NT, 1, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
+    } else {
+      stage2_b3_sw<NT, NE, 0, P>(c0.s, acc, Tc, sm, g, n);
+    }
+  }
+  if (more) store_step_b3<NT, P ^ 1>(t1, c1, ln, row0, st, sm);
+  __syncthreads();
+  live = more;
+  c0 = c1;
+  t0 = t1;
+}
+
+template <int NT, int NE>
+__device__ __forceinline__ void chain_item_b3_e(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
+                                                const Bases<float>& B, B3Smem<NT>& sm) {
   const int tid = threadIdx.x;
-  float acc[kAcc];
-#pragma unroll
-  for (int q = 0; q < kAcc; ++q) acc[q] = 0.f;
-  for (int ti = tile.t0; ti < tile.t1; ++ti) {
-    const Task t = tasks[ti];
-    const uint32_t fl = t.flags;
-    const int sl = (fl & T_SELL) ? 1 : 0, sr = (fl & T_SELR) ? 1 : 0;
-    const uint16_t* Lh = B.Lhi[sl] + t.offL;
-    const uint16_t* Ll = B.Llo[sl] + t.offL;
-    const uint16_t* Rh = B.Rhi[sr] + t.offR;
-    const uint16_t* Rl = B.Rlo[sr] + t.offR;
-    const float* X = B.X + t.offX;
-    const float f = (float)t.f;
-    const int b = t.b, c = t.c;
-    for (int idx = tid; idx < rows * c; idx += kThreads) {
-      const int r = idx / c, j = idx - r * c;
-      const int i = w.row0 + r;
-      float v = 0.f;
-      if (fl & T_IDL) {
-        v = ld_op(X, fl & T_TX, i, j, t.ldX);
-      } else {
-        for (int k = 0; k < b; ++k) {
-          float x = ld_op(X, fl & T_TX, k, j, t.ldX);
-          uint16_t xh = f2bf(x);
-          uint16_t xl = f2bf(x - bf2f(xh));
-          v += mul3(bf2f(ld_op(Lh, fl & T_TL, i, k, t.ldL)), bf2f(ld_op(Ll, fl & T_TL, i, k, t.ldL)), bf2f(xh), bf2f(xl));
-        }
-      }
-      Ts[r * (kMaxDim + 1) + j] = f * v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kAcc; ++q) {
-      const int idx = tid + q * kThreads;
-      const int r = idx / kMaxDim, n = idx - r * kMaxDim;
-      if (r < rows && n < E) {
-        if (fl & T_IDR) {
-          acc[q] += Ts[r * (kMaxDim + 1) + n];
-        } else {
-          float v = 0.f;
-          for (int j = 0; j < c; ++j) {
-            float tv = Ts[r * (kMaxDim + 1) + j];
-            uint16_t th = f2bf(tv);
-            uint16_t tl = f2bf(tv - bf2f(th));
-            v += mul3(bf2f(th), bf2f(tl), bf2f(ld_op(Rh, fl & T_TR, j, n, t.ldR)), bf2f(ld_op(Rl, fl & T_TR, j, n, t.ldR)));
-          }
-          acc[q] += v;
-        }
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < kAcc; ++q) {
-    const int idx = tid + q * kThreads;
-    const int r = idx / kMaxDim, n = idx - r * kMaxDim;
-    if (r < rows && n < E) B.out[tile.offOut + (int64_t)(w.row0 + r) * tile.ldOut + n] = acc[q];
-  }
-}
-
-hipError_t launch_chain_bf16x3(const Tile* tiles, const Work* work, int64_t n_work, const Task* tasks,
-                               const uint16_t* Lhi[2], const uint16_t* Llo[2], const uint16_t* Rhi[2],
-                               const uint16_t* Rlo[2], const float* X, float* out, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  Bf16Args a;
-  for (int i = 0; i < 2; ++i) {
-    a.Lhi[i] = Lhi[i];
-    a.Llo[i] = Llo[i];
-    a.Rhi[i] = Rhi[i];
-    a.Rlo[i] = Rlo[i];
-  }
-  a.X = X;
-  a.out = out;
-  hipLaunchKernelGGL(chain_bf16x3_plain, dim3((unsigned)n_work), dim3(kThreads), 0, s, tiles, work, tasks, a);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ chained product, bf16 split (MFMA)
-// Same output-stationary structure as chain_mfma on v_mfma_f32_16x16x32_bf16
-// (K = 32 per instruction; lane l holds A[l%16][8(l/16)+j] and
-// B[8(l/16)+j][l%16], j = 0..7; result as the f32 16x16x4 instruction).
-// Every product a*b is formed as ah*bh + ah*bl + al*bh (three instructions,
-// FP32 accumulation).  Stage 1 sums over b with lane group g covering the
-// contiguous k range [8 g ks, 8 (g+1) ks) (ks = ceil(b/32) instructions);
-// two 16-column chunks of T = f op(L) op(X) (FP32, re-split into hi/lo)
-// form the 32-wide A operand of stage 2.
-typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ __bf16 bits2bf(uint16_t u) { return __builtin_bit_cast(__bf16, u); }
-
-__device__ __forceinline__ void split8(const float (&x)[8], bf8_t& hi, bf8_t& lo) {
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    uint16_t h = f2bf(x[j]);
-    hi[j] = bits2bf(h);
-    lo[j] = bits2bf(f2bf(x[j] - bf2f(h)));
-  }
-}
-
-__device__ __forceinline__ f4_t mma3(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl, f4_t c) {
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-  return c;
-}
-
-template <int KS8, int NT>
-__global__ __launch_bounds__(256) void chain_bf16x3_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
-                                                         const Task* __restrict__ tasks, Bf16Args B) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const Lane<16 * NT> ln(tid);
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int g = lane >> 4, n = lane & 15;
-  const Work w = work[blockIdx.x];
-  const Tile tile = tiles[w.tile];
   const int wrow0 = w.row0 + wave * 16;
-  if (wrow0 >= tile.a) return;  // no barriers below
-  const int row = wrow0 + n;
-  const bool rowok = row < tile.a;
+  const bool wave_on = wrow0 < tile.a;
   const int E = tile.e;
-  f4_t acc[NT];
+  f32v4 acc[NT], Tc[NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) acc[nt] = f4_t{0, 0, 0, 0};
-  for (int ti = tile.t0; ti < tile.t1; ++ti) {
-    const Task t = tasks[ti];
-    const uint32_t fl = t.flags;
-    const int b = t.b, c = t.c;
-    const int sl = (fl & T_SELL) ? 1 : 0, sr = (fl & T_SELR) ? 1 : 0;
-    const uint16_t* Lh = B.Lhi[sl] + t.offL;
-    const uint16_t* Ll = B.Llo[sl] + t.offL;
-    const uint16_t* Rh = B.Rhi[sr] + t.offR;
-    const uint16_t* Rl = B.Rlo[sr] + t.offR;
-    const float* X = B.X + t.offX;
-    const float f = (float)t.f;
-    const int ks = (b + 31) >> 5;
-    const bool direct = (fl & (T_IDL | T_IDX)) != 0;
-    const bool tl = fl & T_TL, tx = fl & T_TX, tr = fl & T_TR;
-    bf8_t Lrh[KS8], Lrl[KS8];
-    if (!direct) {
-#pragma unroll
-      for (int s8 = 0; s8 < KS8; ++s8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = g * 8 * ks + 8 * s8 + j;
-          uint16_t vh = 0, vl = 0;
-          if (s8 < ks && rowok && k < b) {
-            const int64_t o = tl ? (int64_t)k * t.ldL + row : (int64_t)row * t.ldL + k;
-            vh = Lh[o];
-            vl = Ll[o];
-          }
-          Lrh[s8][j] = bits2bf(vh);
-          Lrl[s8][j] = bits2bf(vl);
-        }
-      }
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = f32v4{0, 0, 0, 0};
+  if (tile.t0 < tile.t1) {
+    Cursor c0{tile.t0, 0, 0};
+    Task t0 = tasks[tile.t0];
+    Task pre = tasks[min(tile.t0 + 1, tile.t1 - 1)];
+    {
+      const Stage<float, NT> st = load_step<float, NT>(t0, B, c0, ln, w.row0);
+      store_step_b3<NT, 0>(t0, c0, ln, w.row0, st, sm);
     }
-    for (int c0 = 0; c0 < c; c0 += 32) {
-      f4_t Tc[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int cb = c0 + 16 * h;
-        f4_t Tt = f4_t{0, 0, 0, 0};
-        if (direct) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int col = cb + 4 * g + r;
-            float v = 0.f;
-            if (rowok && col < c) {
-              if (fl & T_IDL) v = ld_op(X, tx, row, col, t.ldX);
-              else {
-                const int64_t o = tl ? (int64_t)col * t.ldL + row : (int64_t)row * t.ldL + col;
-                v = bf2f(Lh[o]) + bf2f(Ll[o]);
-              }
-            }
-            Tt[r] = v;
-          }
-        } else if (cb < c) {
-          const int m = cb + n;
-          const bool mok = m < c;
-#pragma unroll
-          for (int s8 = 0; s8 < KS8; ++s8) {
-            if (s8 < ks) {
-              float xv[8];
-#pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                const int k = g * 8 * ks + 8 * s8 + j;
-                xv[j] = (mok && k < b) ? ld_op(X, tx, k, m, t.ldX) : 0.f;
-              }
-              bf8_t xh, xl;
-              split8(xv, xh, xl);
-              Tt = mma3(xh, xl, Lrh[s8], Lrl[s8], Tt);
-            }
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Tt[r] *= f;
-        Tc[h] = Tt;
-      }
-      float tv[8];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        tv[r] = Tc[0][r];
-        tv[4 + r] = Tc[1][r];
-      }
-      bf8_t th, tlo;
-      split8(tv, th, tlo);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (nt * 16 < E) {
-          const int col = nt * 16 + n;
-          bf8_t rh, rl;
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int kk = (j < 4) ? c0 + 4 * g + j : c0 + 16 + 4 * g + (j - 4);
-            uint16_t vh = 0, vl = 0;
-            if (kk < c && col < E) {
-              if (fl & T_IDR) {
-                vh = (kk == col) ? (uint16_t)0x3f80 : (uint16_t)0;
-              } else {
-                const int64_t o = tr ? (int64_t)col * t.ldR + kk : (int64_t)kk * t.ldR + col;
-                vh = Rh[o];
-                vl = Rl[o];
-              }
-            }
-            rh[j] = bits2bf(vh);
-            rl[j] = bits2bf(vl);
-          }
-          acc[nt] = mma3(th, tlo, rh, rl, acc[nt]);
-        }
-      }
+    __syncthreads();
+    bool live = true;
+    while (live) {
+      pipe_step_b3<NT, NE, 0>(tile, tasks, B, sm, ln, w.row0, wave_on, wave, g, n, Tc, acc, live, c0, t0, pre);
+      if (!live) break;
+      pipe_step_b3<NT, NE, 1>(tile, tasks, B, sm, ln, w.row0, wave_on, wave, g, n, Tc, acc, live, c0, t0, pre);
     }
   }
+  if (!wave_on) return;
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
+  for (int nt = 0; nt < NE; ++nt) {
     const int col = nt * 16 + n;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int rr = wrow0 + 4 * g + r;
-      if (rr < tile.a && col < E) B.out[tile.offOut + (int64_t)rr * tile.ldOut + col] = acc[nt][r];
+      const int row = wrow0 + 4 * g + r;
+      if (row < tile.a && col < E) B.out[tile.offOut + (int64_t)row * tile.ldOut + col] = acc[nt][r];
     }
   }
 }
 
-hipError_t launch_bf16x3_mfma(const Tile* tiles, const WorkSet& ws, const Task* tasks, const uint16_t* Lhi[2],
-                              const uint16_t* Llo[2], const uint16_t* Rhi[2], const uint16_t* Rlo[2], const float* X,
-                              float* out, hipStream_t s, hipEvent_t (*ev)[2]) {
-  Bf16Args a;
-  for (int i = 0; i < 2; ++i) {
-    a.Lhi[i] = Lhi[i];
-    a.Llo[i] = Llo[i];
-    a.Rhi[i] = Rhi[i];
-    a.Rlo[i] = Rlo[i];
-  }
-  a.X = X;
-  a.out = out;
+template <int NT>
+__global__ __launch_bounds__(256) void chain_b3(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+                                                const Task* __restrict__ tasks, Bases<float> B) {
+  __shared__ B3Smem<NT> sm;
+  const Work w = work[blockIdx.x];
+  const Tile tile = tiles[w.tile];
+  const int ne = (tile.e + 15) >> 4;
+  if (ne <= NeBucket<NT, 1>::value)
+    chain_item_b3_e<NT, NeBucket<NT, 1>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 2>::value)
+    chain_item_b3_e<NT, NeBucket<NT, 2>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 3>::value)
+    chain_item_b3_e<NT, NeBucket<NT, 3>::value>(tile, w, tasks, B, sm);
+  else
+    chain_item_b3_e<NT, NT>(tile, w, tasks, B, sm);
+}
+
+hipError_t launch_bf16x3(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
+                         const hipStream_t* ss, hipEvent_t (*ev)[2]) {
   for (int v = kNumVariants - 1; v >= 0; --v) {
     if (ws.n[v] <= 0) continue;
+    hipStream_t s = ss[v];
     if (ev && ev[v][0]) {
       hipError_t e = hipEventRecord(ev[v][0], s);
       if (e != hipSuccess) return e;
     }
     dim3 grid((unsigned)ws.n[v]), blk(256);
     switch (v) {
-      case 0: hipLaunchKernelGGL((chain_bf16x3_mfma<1, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
-      case 1: hipLaunchKernelGGL((chain_bf16x3_mfma<2, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
-      case 2: hipLaunchKernelGGL((chain_bf16x3_mfma<4, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
-      default: hipLaunchKernelGGL((chain_bf16x3_mfma<8, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, a); break;
+      case 0: hipLaunchKernelGGL((chain_b3<2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 1: hipLaunchKernelGGL((chain_b3<4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      case 2: hipLaunchKernelGGL((chain_b3<8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      default: hipLaunchKernelGGL((chain_b3<16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1051,14 +1006,6 @@ __global__ void f32_to_f64_kernel(const float* in, double* out, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (double)in[i];
 }
-__global__ void split_bf16_kernel(const double* in, uint16_t* hi, uint16_t* lo, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float x = (float)in[i];
-    uint16_t h = f2bf(x);
-    hi[i] = h;
-    lo[i] = f2bf(x - bf2f(h));
-  }
-}
 
 static unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
@@ -1074,10 +1021,6 @@ hipError_t launch_f64_to_f32(const double* in, float* out, int64_t n, hipStream_
 }
 hipError_t launch_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(f32_to_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
-  return hipGetLastError();
-}
-hipError_t launch_split_bf16(const double* in, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(split_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, hi, lo, n);
   return hipGetLastError();
 }
 
