@@ -492,13 +492,40 @@ static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
   return d;
 }
 
-// Work items of the matrix-core kernels, one list per variant (tiles taken
-// in the given order, each cut into kTileRows-row items).
+// Work items of the matrix-core kernels, one list per variant.  Work-groups
+// are dispatched round-robin over the eight XCDs (list position p runs on
+// XCD p % 8), each with its own L2.  The 64-row items of one tile share the
+// op(X) and op(R) slices of every step, so they are placed on the same XCD
+// at consecutive positions of its sequence (they run side by side); tiles
+// go, in the given order (longest first), to the XCD with the least work so
+// far.  Unused positions hold row0 = -1 (the kernels skip them).
+static double task_flops(const Task& t);
+
 static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
                        const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants]) {
+  constexpr int kXcd = 8;
+  std::vector<Work> q[kNumVariants][kXcd];
+  double load[kNumVariants][kXcd] = {};
   for (int t : order) {
-    int v = variant_of(tile_dim(tiles[t], tasks));
-    for (int r = 0; r < tiles[t].a; r += kTileRows) lists[v].push_back({t, r});
+    const int v = variant_of(tile_dim(tiles[t], tasks));
+    double cost = 1.0;
+    for (int k = tiles[t].t0; k < tiles[t].t1; ++k) cost += task_flops(tasks[k]) / std::max(1, tiles[t].a);
+    int x = 0;
+    for (int j = 1; j < kXcd; ++j)
+      if (load[v][j] < load[v][x]) x = j;
+    int rows = 0;
+    for (int r = 0; r < tiles[t].a; r += kTileRows) {
+      q[v][x].push_back({t, r});
+      ++rows;
+    }
+    load[v][x] += cost * std::max(rows, 1);
+  }
+  for (int v = 0; v < kNumVariants; ++v) {
+    size_t m = 0;
+    for (int x = 0; x < kXcd; ++x) m = std::max(m, q[v][x].size());
+    lists[v].clear();
+    for (size_t i = 0; i < m; ++i)
+      for (int x = 0; x < kXcd; ++x) lists[v].push_back(i < q[v][x].size() ? q[v][x][i] : Work{0, -1});
   }
 }
 

@@ -430,6 +430,7 @@ __global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles
                                                   const Task* __restrict__ tasks, Bases<T> B) {
   __shared__ ChainSmem<T, NT> sm;
   const Work w = work[blockIdx.x];
+  if (w.row0 < 0) return;  // unused position of the XCD-ordered list
   chain_item<T, NT>(tiles[w.tile], w, tasks, B, sm);
 }
 
@@ -443,6 +444,7 @@ __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__
   __shared__ ChainSmem<T, NT> sm;
   for (int64_t i = blockIdx.x; i < n_work; i += gridDim.x) {
     const Work w = work[i];
+    if (w.row0 < 0) continue;  // unused position of the XCD-ordered list
     const Tile tile = tiles[w.tile];
     const ProbBases<T> q = pb[tile.prob];
     Bases<T> B;
@@ -741,6 +743,7 @@ __global__ __launch_bounds__(256) void chain_b3(const Tile* __restrict__ tiles, 
                                                 const Task* __restrict__ tasks, Bases<float> B) {
   __shared__ B3Smem<NT> sm;
   const Work w = work[blockIdx.x];
+  if (w.row0 < 0) return;  // unused position of the XCD-ordered list
   const Tile tile = tiles[w.tile];
   const int ne = (tile.e + 15) >> 4;
   if (ne <= NeBucket<NT, 1>::value)
