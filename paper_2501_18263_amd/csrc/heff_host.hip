@@ -1663,6 +1663,8 @@ struct heff_batch {
   heff::DevWorkSet work;
   int grid[heff::kNumVariants] = {0, 0, 0, 0};
   hipStream_t gs = nullptr;
+  hipStream_t vs[heff::kNumVariants] = {};  // captured branches, one per variant
+  hipEvent_t cfork = nullptr, cjoin[heff::kNumVariants] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1677,6 +1679,11 @@ struct heff_batch {
     drop_graph();
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
+    for (int v = 0; v < heff::kNumVariants; ++v) {
+      if (vs[v]) (void)hipStreamDestroy(vs[v]);
+      if (cjoin[v]) (void)hipEventDestroy(cjoin[v]);
+    }
+    if (cfork) (void)hipEventDestroy(cfork);
     if (gs) (void)hipStreamDestroy(gs);
   }
 };
@@ -1795,11 +1802,28 @@ extern "C" int heff_batch_apply(heff_ctx* ctx, heff_batch* b, int use_graph) {
   const Task* tk = b->tasks.as<Task>();
   const ProbBases<float>* pb = b->pb.as<ProbBases<float>>();
   if (!use_graph) {
-    HCHECK(launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, ctx->stream));
+    hipStream_t vs[kNumVariants];
+    fork_variants(ctx, vs);
+    HCHECK(launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, vs));
+    join_variants(ctx);
   } else {
     if (!b->exec) {
+      if (!b->cfork) {
+        HCHECK(hipEventCreateWithFlags(&b->cfork, hipEventDisableTiming));
+        for (int v = 0; v < kNumVariants; ++v) {
+          HCHECK(hipStreamCreateWithFlags(&b->vs[v], hipStreamNonBlocking));
+          HCHECK(hipEventCreateWithFlags(&b->cjoin[v], hipEventDisableTiming));
+        }
+      }
+      // the variant launches form parallel branches of the captured graph
       HCHECK(hipStreamBeginCapture(b->gs, hipStreamCaptureModeThreadLocal));
-      hipError_t e = launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, b->gs);
+      hipError_t e = hipEventRecord(b->cfork, b->gs);
+      for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) e = hipStreamWaitEvent(b->vs[v], b->cfork, 0);
+      if (e == hipSuccess) e = launch_mfma_batch_f32(tl, b->work.ws, tk, pb, b->x, b->y, b->grid, b->vs);
+      for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
+        e = hipEventRecord(b->cjoin[v], b->vs[v]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->gs, b->cjoin[v], 0);
+      }
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(b->gs, &g);
       HCHECK(e);

@@ -109,8 +109,9 @@ inline hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Ta
   return launch_mfma_f32(tiles, ws, tasks, b, a, ev);
 }
 // grid[v]: persistent work-groups of variant v
+// s[v]: stream of variant v (the variants may run concurrently)
 hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, const ProbBases<float>* pb,
-                                 const float* X, float* out, const int grid[kNumVariants], hipStream_t s);
+                                 const float* X, float* out, const int grid[kNumVariants], const hipStream_t* s);
 // split-precision (bf16 hi+lo, FP32 accumulation) product on the FP32 operand arenas
 hipError_t launch_bf16x3(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
                          const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);

@@ -460,9 +460,10 @@ __global__ __launch_bounds__(256) void chain_mfma_batch(const Tile* __restrict__
 }
 
 hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, const ProbBases<float>* pb,
-                                 const float* X, float* out, const int grid[kNumVariants], hipStream_t s) {
+                                 const float* X, float* out, const int grid[kNumVariants], const hipStream_t* ss) {
   for (int v = kNumVariants - 1; v >= 0; --v) {
     if (ws.n[v] <= 0) continue;
+    hipStream_t s = ss[v];
     dim3 gr((unsigned)grid[v]), blk(256);
     switch (v) {
       case 0: hipLaunchKernelGGL((chain_mfma_batch<float, 2>), gr, blk, 0, s, tiles, ws.w[v], ws.n[v], tasks, pb, X, out); break;
