@@ -217,6 +217,58 @@ def converged_energies(args):
     return out
 
 
+def bench_backward(args):
+    """Differentiation workload (N=16, D=256): time of the reverse-mode
+    backward of E = <psi|H_eff|psi> (dE/dpsi and both operand-arena
+    gradients) in FP64 and FP32, and of the orbital-rotation gradient for all
+    N(N-1)/2 orbital pairs (one block build and one product per pair)."""
+    import numpy as np
+    import torch
+
+    from paper_2501_18263_amd import heff, synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    p = synth.make_problem(16, 256, 5)
+    ctx = heff.Context(0)
+    B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32))
+    x = torch.tensor(synth.random_psi(p), device="cuda")
+    out = {}
+    for name, pr, xx in (("fp64", heff.FP64, x), ("fp32", heff.FP32, x.float())):
+        B.energy_backward(xx, prec=pr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            B.energy_backward(xx, prec=pr)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"backward_ms": 1e3 * dt}
+        log("%s backward: %.3f ms" % (name, 1e3 * dt))
+    d64 = B.energy_backward(x)
+    d32 = B.energy_backward(x.float(), prec=heff.FP32)
+    rel = [float(torch.linalg.vector_norm(a.double() - b.double()) / torch.linalg.vector_norm(a.double()))
+           for a, b in zip(d64, d32)]
+    out["fp32_vs_fp64_rel"] = {"dpsi": rel[0], "dL": rel[1], "dR": rel[2]}
+    pairs = [(a, b) for a in range(16) for b in range(a + 1, 16)]
+    t0 = time.perf_counter()
+    g = heff.kappa_gradient(ctx, p, x, pairs)
+    out["kappa_gradient"] = {"pairs": len(pairs), "seconds": time.perf_counter() - t0,
+                             "norm": float(np.linalg.norm(g))}
+    log("kappa gradient: %d pairs in %.2f s" % (len(pairs), out["kappa_gradient"]["seconds"]))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.apply(x, torch.empty_like(x))
+    torch.cuda.synchronize()
+    out["product_ms"] = 1e3 * (time.perf_counter() - t0) / args.steps
+    for name in ("fp64", "fp32"):
+        out[name]["products_equivalent"] = out[name]["backward_ms"] / out["product_ms"]
+    res = {"metric": "backward of <psi|H_eff|psi> (N=16, D=256)", "value": out["fp64"]["backward_ms"],
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": out["fp64"]["backward_ms"],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "two-site energy backward, N=16 D=256 seed 5",
+                                           "psi_dim": int(B.n_elem)},
+           "details": out}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +280,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precs", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "backward"], default="single")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--converge", type=int, default=0,
                     help="also run each precision's Davidson to convergence (at most this many steps) "
@@ -248,6 +300,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "backward":
+        bench_backward(args)
         return
 
     import numpy as np  # noqa: F401
