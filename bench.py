@@ -299,8 +299,14 @@ def main():
         sys.exit(2)
 
     if args.workload == "batched":
-        bench_batched(args)
-        return
+        # This workload (64 problems built and run in one process) ended in a
+        # host segmentation fault after the kernels moved to two work-groups
+        # per CU and tree-dispatched stage instances; its cause is not found,
+        # so it stays switched off.  The batched parity test (a few problems,
+        # graph replays) passes with these kernels.
+        print("bench.py: the batched workload is switched off (a host segmentation fault with the "
+              "current kernels is not yet explained)", file=sys.stderr)
+        sys.exit(3)
     if args.workload == "backward":
         bench_backward(args)
         return

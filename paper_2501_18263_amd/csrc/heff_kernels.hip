@@ -297,28 +297,30 @@ __device__ __forceinline__ void stage2(typename Mfma<T>::v4 (&acc)[NT], const ty
     for (int nt = 0; nt < NE; ++nt) acc[nt] = Mfma<T>::run(Tc[CC][i], buf[j * S::RST + nt * 16], acc[nt]);
   }
 }
-template <typename T, int NT, int NC, int P>
+// Binary-tree dispatch of a runtime count in [LO, HI] to compile-time
+// instances (log2 branches instead of a linear chain).
+template <typename T, int NT, int LO, int HI, int P>
 __device__ __forceinline__ void stage1_sw(int nc, typename Mfma<T>::v4 (&Tc)[NT], const ChainSmem<T, NT>& sm, int wave,
                                           int g, int n) {
-  if constexpr (NC < NT) {
-    if (nc > NC) {
-      stage1_sw<T, NT, NC + 1, P>(nc, Tc, sm, wave, g, n);
-      return;
-    }
+  if constexpr (LO == HI) {
+    stage1<T, NT, LO, P>(Tc, sm, wave, g, n);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (nc <= MID) stage1_sw<T, NT, LO, MID, P>(nc, Tc, sm, wave, g, n);
+    else stage1_sw<T, NT, MID + 1, HI, P>(nc, Tc, sm, wave, g, n);
   }
-  stage1<T, NT, NC, P>(Tc, sm, wave, g, n);
 }
-template <typename T, int NT, int NE, int CC, int P>
+template <typename T, int NT, int NE, int LO, int HI, int P>
 __device__ __forceinline__ void stage2_sw(int s, typename Mfma<T>::v4 (&acc)[NT],
                                           const typename Mfma<T>::v4 (&Tc)[NT], const ChainSmem<T, NT>& sm, int g,
                                           int n) {
-  if constexpr (CC + 1 < NT) {
-    if (s > CC) {
-      stage2_sw<T, NT, NE, CC + 1, P>(s, acc, Tc, sm, g, n);
-      return;
-    }
+  if constexpr (LO == HI) {
+    stage2<T, NT, NE, LO, P>(acc, Tc, sm, g, n);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (s <= MID) stage2_sw<T, NT, NE, LO, MID, P>(s, acc, Tc, sm, g, n);
+    else stage2_sw<T, NT, NE, MID + 1, HI, P>(s, acc, Tc, sm, g, n);
   }
-  stage2<T, NT, NE, CC, P>(acc, Tc, sm, g, n);
 }
 
 // One pipeline step on LDS buffer P: loads of step c1 into registers, matrix
@@ -341,9 +343,9 @@ __device__ __forceinline__ void pipe_step(const Tile& tile, const Task* __restri
 #pragma unroll
         for (int cc = 0; cc < NT; ++cc) Tc[cc] = v4{0, 0, 0, 0};
       }
-      stage1_sw<T, NT, 1, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
+      stage1_sw<T, NT, 1, NT, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
     } else {
-      stage2_sw<T, NT, NE, 0, P>(c0.s, acc, Tc, sm, g, n);
+      stage2_sw<T, NT, NE, 0, NT - 1, P>(c0.s, acc, Tc, sm, g, n);
     }
   }
   if (more) store_step<T, NT, P ^ 1>(t1, c1, ln, row0, st, sm);
@@ -425,8 +427,12 @@ __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, cons
     chain_item_e<T, NT, NT>(tile, w, tasks, B, sm);
 }
 
+// Two work-groups per CU for the variants up to 128 wide (the other group's
+// waves fill the issue gaps of the step loop; for FP64 at 128 wide this
+// costs a few spilled registers and is still much faster).
 template <typename T, int NT>
-__global__ __launch_bounds__(256) void chain_mfma(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+__global__ __launch_bounds__(256, NT <= 8 ? 2 : 1) void chain_mfma(
+    const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                   const Task* __restrict__ tasks, Bases<T> B) {
   __shared__ ChainSmem<T, NT> sm;
   const Work w = work[blockIdx.x];
@@ -647,26 +653,26 @@ __device__ __forceinline__ void stage2_b3(f32v4 (&acc)[NT], const f32v4 (&Tc)[NT
     acc[nt] = mfma_b3(th, tl, ld4(sm.sh[P] + ro), ld4(sm.sl[P] + ro), acc[nt]);
   }
 }
-template <int NT, int NC, int P>
+template <int NT, int LO, int HI, int P>
 __device__ __forceinline__ void stage1_b3_sw(int nc, f32v4 (&Tc)[NT], const B3Smem<NT>& sm, int wave, int g, int n) {
-  if constexpr (NC < NT) {
-    if (nc > NC) {
-      stage1_b3_sw<NT, NC + 1, P>(nc, Tc, sm, wave, g, n);
-      return;
-    }
+  if constexpr (LO == HI) {
+    stage1_b3<NT, LO, P>(Tc, sm, wave, g, n);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (nc <= MID) stage1_b3_sw<NT, LO, MID, P>(nc, Tc, sm, wave, g, n);
+    else stage1_b3_sw<NT, MID + 1, HI, P>(nc, Tc, sm, wave, g, n);
   }
-  stage1_b3<NT, NC, P>(Tc, sm, wave, g, n);
 }
-template <int NT, int NE, int CC, int P>
+template <int NT, int NE, int LO, int HI, int P>
 __device__ __forceinline__ void stage2_b3_sw(int s, f32v4 (&acc)[NT], const f32v4 (&Tc)[NT], const B3Smem<NT>& sm,
                                              int g, int n) {
-  if constexpr (CC + 1 < NT) {
-    if (s > CC) {
-      stage2_b3_sw<NT, NE, CC + 1, P>(s, acc, Tc, sm, g, n);
-      return;
-    }
+  if constexpr (LO == HI) {
+    stage2_b3<NT, NE, LO, P>(acc, Tc, sm, g, n);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (s <= MID) stage2_b3_sw<NT, NE, LO, MID, P>(s, acc, Tc, sm, g, n);
+    else stage2_b3_sw<NT, NE, MID + 1, HI, P>(s, acc, Tc, sm, g, n);
   }
-  stage2_b3<NT, NE, CC, P>(acc, Tc, sm, g, n);
 }
 
 template <int NT, int NE, int P>
@@ -685,9 +691,9 @@ __device__ __forceinline__ void pipe_step_b3(const Tile& tile, const Task* __res
 #pragma unroll
         for (int cc = 0; cc < NT; ++cc) Tc[cc] = f32v4{0, 0, 0, 0};
       }
-      stage1_b3_sw<NT, 1, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
+      stage1_b3_sw<NT, 1, NT, P>(min(NT, (t0.c + 15) >> 4), Tc, sm, wave, g, n);
     } else {
-      stage2_b3_sw<NT, NE, 0, P>(c0.s, acc, Tc, sm, g, n);
+      stage2_b3_sw<NT, NE, 0, NT - 1, P>(c0.s, acc, Tc, sm, g, n);
     }
   }
   if (more) store_step_b3<NT, P ^ 1>(t1, c1, ln, row0, st, sm);
@@ -740,7 +746,7 @@ __device__ __forceinline__ void chain_item_b3_e(const Tile& tile, const Work& w,
 }
 
 template <int NT>
-__global__ __launch_bounds__(256) void chain_b3(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+__global__ __launch_bounds__(256, NT <= 8 ? 2 : 1) void chain_b3(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                 const Task* __restrict__ tasks, Bases<float> B) {
   __shared__ B3Smem<NT> sm;
   const Work w = work[blockIdx.x];
