@@ -496,36 +496,66 @@ static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
 // are dispatched round-robin over the eight XCDs (list position p runs on
 // XCD p % 8), each with its own L2.  The 64-row items of one tile share the
 // op(X) and op(R) slices of every step, so they are placed on the same XCD
-// at consecutive positions of its sequence (they run side by side); tiles
-// go, in the given order (longest first), to the XCD with the least work so
-// far.  Unused positions hold row0 = -1 (the kernels skip them).
+// at consecutive positions of its sequence (they run side by side).  Tiles
+// with the same key form a group that goes to one XCD as consecutive items;
+// groups go, longest first, to the XCD with the least work so far.  Without
+// keys every tile is its own group (grouping the product's output blocks by
+// their right sector, which share the sequence of op(R) blocks, raised the
+// HBM traffic: it separated the blocks that share op(L) and psi).  Unused
+// positions hold row0 = -1 (the kernels skip them).
 static double task_flops(const Task& t);
 
 static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
-                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants]) {
+                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants],
+                       const std::vector<int>* key = nullptr) {
   constexpr int kXcd = 8;
-  std::vector<Work> q[kNumVariants][kXcd];
-  double load[kNumVariants][kXcd] = {};
+  // groups per variant, in first-appearance order of `order` (longest first)
+  std::vector<std::vector<int>> groups[kNumVariants];
+  std::vector<double> gcost[kNumVariants];
+  std::map<std::pair<int, int>, int> gid;
   for (int t : order) {
     const int v = variant_of(tile_dim(tiles[t], tasks));
     double cost = 1.0;
     for (int k = tiles[t].t0; k < tiles[t].t1; ++k) cost += task_flops(tasks[k]) / std::max(1, tiles[t].a);
-    int x = 0;
-    for (int j = 1; j < kXcd; ++j)
-      if (load[v][j] < load[v][x]) x = j;
-    int rows = 0;
-    for (int r = 0; r < tiles[t].a; r += kTileRows) {
-      q[v][x].push_back({t, r});
-      ++rows;
+    cost *= std::max(1, (tiles[t].a + kTileRows - 1) / kTileRows);
+    int g;
+    if (key) {
+      auto it = gid.find({v, (*key)[t]});
+      if (it == gid.end()) {
+        g = (int)groups[v].size();
+        gid[{v, (*key)[t]}] = g;
+        groups[v].emplace_back();
+        gcost[v].push_back(0.0);
+      } else {
+        g = it->second;
+      }
+    } else {
+      g = (int)groups[v].size();
+      groups[v].emplace_back();
+      gcost[v].push_back(0.0);
     }
-    load[v][x] += cost * std::max(rows, 1);
+    groups[v][g].push_back(t);
+    gcost[v][g] += cost;
   }
   for (int v = 0; v < kNumVariants; ++v) {
+    std::vector<int> gorder(groups[v].size());
+    for (size_t i = 0; i < gorder.size(); ++i) gorder[i] = (int)i;
+    std::stable_sort(gorder.begin(), gorder.end(), [&](int a, int b) { return gcost[v][a] > gcost[v][b]; });
+    std::vector<Work> q[kXcd];
+    double load[kXcd] = {};
+    for (int g : gorder) {
+      int x = 0;
+      for (int j = 1; j < kXcd; ++j)
+        if (load[j] < load[x]) x = j;
+      for (int t : groups[v][g])
+        for (int r = 0; r < tiles[t].a; r += kTileRows) q[x].push_back({t, r});
+      load[x] += gcost[v][g];
+    }
     size_t m = 0;
-    for (int x = 0; x < kXcd; ++x) m = std::max(m, q[v][x].size());
+    for (int x = 0; x < kXcd; ++x) m = std::max(m, q[x].size());
     lists[v].clear();
     for (size_t i = 0; i < m; ++i)
-      for (int x = 0; x < kXcd; ++x) lists[v].push_back(i < q[v][x].size() ? q[v][x][i] : Work{0, -1});
+      for (int x = 0; x < kXcd; ++x) lists[v].push_back(i < q[x].size() ? q[x][i] : Work{0, -1});
   }
 }
 
