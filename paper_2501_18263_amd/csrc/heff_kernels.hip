@@ -427,11 +427,12 @@ __device__ __forceinline__ void chain_item(const Tile& tile, const Work& w, cons
     chain_item_e<T, NT, NT>(tile, w, tasks, B, sm);
 }
 
-// Two work-groups per CU for the variants up to 128 wide (the other group's
-// waves fill the issue gaps of the step loop; for FP64 at 128 wide this
-// costs a few spilled registers and is still much faster).
+// Several work-groups per CU for the variants up to 128 wide (the other
+// groups' waves fill the issue gaps and memory waits of the step loop): two
+// for FP64 (at 128 wide this costs a few spilled registers and is still much
+// faster), three for FP32.
 template <typename T, int NT>
-__global__ __launch_bounds__(256, NT <= 8 ? 2 : 1) void chain_mfma(
+__global__ __launch_bounds__(256, NT <= 8 ? (sizeof(T) == 4 ? 3 : 2) : 1) void chain_mfma(
     const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                   const Task* __restrict__ tasks, Bases<T> B) {
   __shared__ ChainSmem<T, NT> sm;
@@ -746,7 +747,7 @@ __device__ __forceinline__ void chain_item_b3_e(const Tile& tile, const Work& w,
 }
 
 template <int NT>
-__global__ __launch_bounds__(256, NT <= 8 ? 2 : 1) void chain_b3(const Tile* __restrict__ tiles, const Work* __restrict__ work,
+__global__ __launch_bounds__(256, NT <= 8 ? 3 : 1) void chain_b3(const Tile* __restrict__ tiles, const Work* __restrict__ work,
                                                 const Task* __restrict__ tasks, Bases<float> B) {
   __shared__ B3Smem<NT> sm;
   const Work w = work[blockIdx.x];
