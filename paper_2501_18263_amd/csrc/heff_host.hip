@@ -495,29 +495,51 @@ static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
 // Work items of the matrix-core kernels, one list per variant.  Work-groups
 // are dispatched round-robin over the eight XCDs (list position p runs on
 // XCD p % 8), each with its own L2.  The 64-row items of one tile share the
-// op(X) and op(R) slices of every step, so they are placed on the same XCD
-// at consecutive positions of its sequence (they run side by side).  Tiles
-// with the same key form a group that goes to one XCD as consecutive items;
-// groups go, longest first, to the XCD with the least work so far.  Without
-// keys every tile is its own group (grouping the product's output blocks by
-// their right sector, which share the sequence of op(R) blocks, raised the
-// HBM traffic: it separated the blocks that share op(L) and psi).  Unused
-// positions hold row0 = -1 (the kernels skip them).
+// op(X) and op(R) slices of every step, so they are placed on the same XCD.
+// Tiles with the same key form a group that goes to one XCD; groups go,
+// largest first, to the XCD with the least work so far.  Without keys every
+// tile is its own group (grouping the product's output blocks by their
+// right sector, which share the sequence of op(R) blocks, raised the HBM
+// traffic: it separated the blocks that share op(L) and psi).  Each XCD then
+// starts its longest items first (a longest-processing-time order; items of
+// one tile have the same estimate and stay adjacent, so they run side by
+// side).  Unused positions hold row0 = -1 (the kernels skip them).
 static double task_flops(const Task& t);
+
+// Estimated run time of one 64-row work item of a tile, in units of one
+// 16x16x4 matrix instruction per wave: every pipeline step costs a fixed
+// overhead (loads, LDS traffic, barrier) of about kStepCost instructions
+// plus its matrix work, 4 ceil(c/16) instructions per stage-1 step and 4 NE
+// per stage-2 step (NE = the output-width bucket of the kernel instance).
+static double item_cost(const Tile& tile, const std::vector<Task>& tasks) {
+  constexpr double kStepCost = 8.0;
+  const int v = variant_of(tile_dim(tile, tasks));
+  const int nt = 2 << v;
+  const int ne = (tile.e + 15) / 16;
+  int neb = nt;
+  for (int q = 1; q <= 3; ++q)
+    if (ne <= std::max(1, nt * q / 4)) { neb = std::max(1, nt * q / 4); break; }
+  double cost = 0.0;
+  for (int k = tile.t0; k < tile.t1; ++k) {
+    const int nb = (tasks[k].b + 15) / 16, nc = (tasks[k].c + 15) / 16;
+    cost += nb * (kStepCost + 4.0 * std::min(nc, nt)) + nc * (kStepCost + 4.0 * neb);
+  }
+  return cost;
+}
 
 static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
                        const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants],
                        const std::vector<int>* key = nullptr) {
   constexpr int kXcd = 8;
-  // groups per variant, in first-appearance order of `order` (longest first)
+  std::vector<double> icost(tiles.size(), 0.0);
+  for (size_t t = 0; t < tiles.size(); ++t) icost[t] = item_cost(tiles[t], tasks);
+  // groups per variant, in first-appearance order of `order`
   std::vector<std::vector<int>> groups[kNumVariants];
   std::vector<double> gcost[kNumVariants];
   std::map<std::pair<int, int>, int> gid;
   for (int t : order) {
     const int v = variant_of(tile_dim(tiles[t], tasks));
-    double cost = 1.0;
-    for (int k = tiles[t].t0; k < tiles[t].t1; ++k) cost += task_flops(tasks[k]) / std::max(1, tiles[t].a);
-    cost *= std::max(1, (tiles[t].a + kTileRows - 1) / kTileRows);
+    const double cost = icost[t] * std::max(1, (tiles[t].a + kTileRows - 1) / kTileRows);
     int g;
     if (key) {
       auto it = gid.find({v, (*key)[t]});
@@ -551,6 +573,9 @@ static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& 
         for (int r = 0; r < tiles[t].a; r += kTileRows) q[x].push_back({t, r});
       load[x] += gcost[v][g];
     }
+    for (int x = 0; x < kXcd; ++x)
+      std::stable_sort(q[x].begin(), q[x].end(),
+                       [&](const Work& a, const Work& b) { return icost[a.tile] > icost[b.tile]; });
     size_t m = 0;
     for (int x = 0; x < kXcd; ++x) m = std::max(m, q[x].size());
     lists[v].clear();
