@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 KERNEL_SRC = [os.path.join(ROOT, "paper_2501_18263_amd", "csrc", f) for f in ("heff_kernels.hip", "heff_host.hip")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_mfma_f64_n40_d4096.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chain_dma_f64_n40_d4096.json")
 
 
 def kernel_source_hash():
@@ -415,8 +415,9 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[head],
             "traffic": measured_traffic(v) if head == "fp64" else None,
-            "kernel": "chain_mfma variant %d (output width and task middle dimension <= %d)" % (
-                v, [32, 64, 128, 256][v]),
+            "kernel": "%s<%s, %d> variant %d (output width and task middle dimension <= %d)" % (
+                "chain_dma" if head == "fp64" and v <= 2 else "chain_mfma", "double" if head == "fp64" else "float",
+                [2, 4, 8, 16][v], v, [32, 64, 128, 256][v]),
             "flops_per_launch": vst[v][0], "avg_launch_ms": avg_s * 1e3,
             "mfma_flops_per_launch": ist[v][0], "mfma_issue_efficiency": vst[v][0] / max(ist[v][0], 1.0),
             "pipeline_steps_per_launch": ist[v][1], "pipeline_steps_longest_group": ist[v][2]}

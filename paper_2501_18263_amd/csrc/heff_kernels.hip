@@ -484,6 +484,456 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
   return hipSuccess;
 }
 
+// ------------------------------------------------------------------ chained product, LDS-DMA pipeline
+// FP64, output widths up to 128.  Same work items, task order and
+// per-element arithmetic as chain_mfma (f folded into the op(L) value, the
+// same MFMA sequence; results are bitwise identical), but the operand slices
+// go straight from global memory to LDS with global_load_lds_dword: each
+// wave instruction moves one dword per lane into 256 consecutive LDS bytes
+// (LDS address = M0 + 4 lane; the global address is per lane).  No staging
+// registers are needed, so the slices pass through a ring of three LDS
+// buffers: the loads of step s + 2 are in flight while step s computes,
+// which hides two steps of memory latency instead of one.  (For FP32, with
+// three work-groups per CU hiding the latency already, the register-staged
+// kernel measured faster, so FP32 keeps it.)
+//
+// Every slice is held as 16 x 16 blocks of 256 elements.  Element (k, m) of
+// a block (k: contraction index of the step, m: row or column of the other
+// operand) sits at
+//   N  16 k + m          when the operand is stored with k as its row index,
+//   T  16 m + (k ^ m)    when it is stored with k contiguous.
+// Each layout puts one wave instruction's 256 bytes on 256 contiguous bytes
+// of global rows (a permutation inside them) and lets the 64 lanes of every
+// operand read hit distinct LDS banks (two lanes per bank pair, the minimum
+// for 512 bytes).  Entries past the operand's extent are loaded
+// from clamped (in-block) addresses and masked at read time: op(L) values
+// with k >= b and stage-2 T values with j >= c are replaced by zero, the
+// factor f multiplies the op(L) value.  Identity operands: op(L) = I is
+// generated in registers, op(X) = I and op(R) = I are written to the ring
+// with LDS stores.
+namespace dmak {
+
+
+// Ring depth and work-groups per CU.  Two work-groups per CU (the other
+// group's matrix work fills this one's barrier and issue time) with a
+// three-slot ring measured faster than one work-group with a four-slot
+// ring.  The kernel must not spill: a spill reload waits for every
+// outstanding load of the wave, ring loads included.
+template <typename T, int NT>
+struct Cfg {
+  static_assert(sizeof(T) == 8, "ring kernel is the FP64 path");
+  static constexpr int stages = 3;
+  static constexpr int groups = 2;
+};
+typedef __attribute__((address_space(3))) char lds_char;
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const lds_char*)p);
+}
+__device__ __forceinline__ const char* sgpr_ptr(const char* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const char*)(((uint64_t)hi << 32) | lo);
+}
+// LDS[m0 + 4 lane] = dword at sbase + voff (bytes).  A global load into
+// LDS needs one wait state after the write of M0.
+__device__ __forceinline__ void dma(const char* sbase, uint32_t voff, uint32_t m0) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(sbase), "s"(m0)
+               : "memory");
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// wait until at most n vector-memory instructions of this wave are
+// outstanding (n rounded down to even, at most 62: waiting for fewer is
+// always safe); binary tree over the even counts
+template <int LO, int HI>
+__device__ __forceinline__ void wait_vm_tree(int n) {
+  if constexpr (LO == HI) {
+    wait_vm<LO>();
+  } else {
+    constexpr int MID = ((LO + HI) / 4) * 2;
+    if (n <= MID + 1) wait_vm_tree<LO, MID>(n);
+    else wait_vm_tree<MID + 2, HI>(n);
+  }
+}
+__device__ __forceinline__ void wait_vm_le(int n) { wait_vm_tree<0, 62>(n < 62 ? n : 62); }
+// barrier that orders LDS accesses only (a full __syncthreads would also
+// wait for every outstanding global load, including the ring's)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T, int NT>
+struct Smem {
+  static constexpr int S = Cfg<T, NT>::stages;
+  T xs[S][NT * 256];  // op(X) or op(R) slice, NT blocks
+  T ls[S][4 * 256];   // op(L) slice, one block per wave
+};
+
+// What the matrix work of a step needs (filled when its loads are issued),
+// packed to keep the three records of the ring in few scalar registers:
+// bc = b | c << 16; m = flags (bits 0-8) | ph << 9 | valid << 10 |
+// cnt << 11 (ring loads per wave, < 32) | s << 16 (slice index).
+struct Rec {
+  double f;
+  uint32_t bc, m;
+  __device__ __forceinline__ int b() const { return (int)(bc & 0xffff); }
+  __device__ __forceinline__ int c() const { return (int)(bc >> 16); }
+  __device__ __forceinline__ uint32_t flags() const { return m & 0x1ff; }
+  __device__ __forceinline__ int ph() const { return (int)((m >> 9) & 1); }
+  __device__ __forceinline__ bool valid() const { return (m >> 10) & 1; }
+  __device__ __forceinline__ int cnt() const { return (int)((m >> 11) & 31); }
+  __device__ __forceinline__ int s() const { return (int)(m >> 16); }
+};
+template <typename T, int NT>
+using Ring = Rec[Cfg<T, NT>::stages];
+
+// Per-lane constants.  Lane l = 16 g + n.  In a 256-byte window q of a
+// block (32 elements, two dwords each) lane l writes dword l & 1 of element
+// 32 q + l / 2; its stored (row, column) is, for the N layout,
+// (k, m) = (2 q + y, mcol), for the T layout (m, k) = (2 q + y, cx ^ 2 q).
+typedef int i4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct LaneC {
+  static constexpr int A = 2;  // block rows per window
+  int lane, g, n, y, mcol, cx, h;
+  i4 tp;  // T position of (k = 4j + g, m = n)
+  __device__ __forceinline__ explicit LaneC(int tid) {
+    lane = tid & 63;
+    g = lane >> 4;
+    n = lane & 15;
+    y = lane >> 5;
+    mcol = (lane >> 1) & 15;
+    h = lane & 1;
+    cx = mcol ^ y;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tp[j] = 16 * n + ((4 * j + g) ^ n);
+  }
+};
+
+// Clamped scalar start of a slice block: the block's base element offset
+// sb (relative to the stored block) is limited to the last stored element
+// `end`; rel is how far lanes may reach past it.
+struct Span {
+  uint32_t sb, rel;
+  __device__ __forceinline__ Span(uint32_t sb0, uint32_t end) {
+    sb = sb0 < end ? sb0 : end;
+    rel = end - sb;
+  }
+};
+
+// ring loads of one op(X)/op(L)-style window: element offset (rowi, z)
+template <typename T>
+__device__ __forceinline__ void dma_window(const char* base, const Span& sp, const LaneC<T>& lc, int q, bool kr,
+                                           uint32_t ld, uint32_t m0) {
+  constexpr int A = LaneC<T>::A;
+  const uint32_t rowi = (uint32_t)(A * q + lc.y);
+  const uint32_t z = kr ? (uint32_t)lc.mcol : (uint32_t)(lc.cx ^ (A * q));
+  uint32_t off = rowi * ld + z;
+  off = off < sp.rel ? off : sp.rel;
+  dma(sgpr_ptr(base + (uint64_t)sp.sb * sizeof(T)), off * (uint32_t)sizeof(T) + 4u * lc.h, m0);
+}
+
+// Issue the ring loads of the step at cursor (cu, t) into slot KI and fill
+// its record; then advance the cursor (ivalid false past the tile's tasks).
+template <typename T, int NT, int NE, int KI>
+__device__ __forceinline__ void issue(Rec& rec, Cursor& cu, Task& t, Task& pre, bool& ivalid,
+                                      const Task* __restrict__ tasks, int t1, const Bases<T>& B, Smem<T, NT>& sm,
+                                      const LaneC<T>& lc, int row0, int wave) {
+  constexpr int WPB = sizeof(T) / 4;  // windows of one block per wave
+  constexpr int LW = sizeof(T);       // windows of one op(L) block
+  constexpr int BB = 256 * sizeof(T); // bytes of one block
+  if (!ivalid) {
+    rec.m = 0;
+    return;
+  }
+  const uint32_t fl = t.flags;
+  rec.f = t.f;
+  rec.bc = (uint32_t)t.b | ((uint32_t)t.c << 16);
+  const int s16 = 16 * cu.s;
+  const int tid = threadIdx.x;
+  int cnt = 0;
+  if (cu.ph == 0) {
+    const int nc = min(NT, (t.c + 15) >> 4);
+    const bool kr = !(fl & T_TX);
+    if (fl & T_IDX) {
+      const int E = tid;
+      const int k = kr ? (E >> 4) : ((E & 15) ^ (E >> 4));
+      const int m = kr ? (E & 15) : (E >> 4);
+#pragma unroll
+      for (int cc = 0; cc < NT; ++cc)
+        if (cc < nc) sm.xs[KI][cc * 256 + E] = T(s16 + k == 16 * cc + m ? 1 : 0);
+    } else {
+      const uint32_t ld = t.ldX;
+      const char* xb = (const char*)(pick((fl & T_SELX) != 0, B.X[0], B.X[1]) + t.offX);
+      const uint32_t end = kr ? (uint32_t)(t.b - 1) * ld + (t.c - 1) : (uint32_t)(t.c - 1) * ld + (t.b - 1);
+      const uint32_t step = kr ? 16u : 16u * ld;
+      uint32_t sb0 = kr ? (uint32_t)s16 * ld : (uint32_t)s16;
+      const uint32_t m0 = lds_addr(&sm.xs[KI][0]);
+#pragma unroll 1
+      for (int cc = 0; cc < nc; ++cc, sb0 += step) {
+        const Span sp(sb0, end);
+#pragma unroll
+        for (int u = 0; u < WPB; ++u) {
+          const int q = wave * WPB + u;
+          dma_window<T>(xb, sp, lc, q, kr, ld, m0 + cc * BB + q * 256);
+        }
+      }
+      cnt += nc * WPB;
+    }
+    if (!(fl & T_IDL)) {
+      const bool kr = (fl & T_TL) != 0;
+      const uint32_t ld = t.ldL;
+      const char* lb = (const char*)(pick((fl & T_SELL) != 0, B.L[0], B.L[1]) + t.offL);
+      const int r0 = row0 + 16 * wave;
+      const uint32_t end = kr ? (uint32_t)(t.b - 1) * ld + (t.a - 1) : (uint32_t)(t.a - 1) * ld + (t.b - 1);
+      const Span sp(kr ? (uint32_t)s16 * ld + r0 : (uint32_t)r0 * ld + s16, end);
+      const uint32_t m0 = lds_addr(&sm.ls[KI][wave * 256]);
+#pragma unroll
+      for (int q = 0; q < LW; ++q) dma_window<T>(lb, sp, lc, q, kr, ld, m0 + q * 256);
+      cnt += LW;
+    }
+  } else {
+    const bool kr = !(fl & T_TR);
+    if (fl & T_IDR) {
+      const int E = tid;
+      const int j = kr ? (E >> 4) : ((E & 15) ^ (E >> 4));
+      const int col = kr ? (E & 15) : (E >> 4);
+#pragma unroll
+      for (int nt = 0; nt < NE; ++nt) sm.xs[KI][nt * 256 + E] = T(s16 + j == 16 * nt + col ? 1 : 0);
+    } else {
+      const uint32_t ld = t.ldR;
+      const char* rb = (const char*)(pick((fl & T_SELR) != 0, B.R[0], B.R[1]) + t.offR);
+      const uint32_t end = kr ? (uint32_t)(t.c - 1) * ld + (t.e - 1) : (uint32_t)(t.e - 1) * ld + (t.c - 1);
+      const uint32_t step = kr ? 16u : 16u * ld;
+      uint32_t sb0 = kr ? (uint32_t)s16 * ld : (uint32_t)s16;
+      const uint32_t m0 = lds_addr(&sm.xs[KI][0]);
+#pragma unroll 1
+      for (int nt = 0; nt < NE; ++nt, sb0 += step) {
+        const Span sp(sb0, end);
+#pragma unroll
+        for (int u = 0; u < WPB; ++u) {
+          const int q = wave * WPB + u;
+          dma_window<T>(rb, sp, lc, q, kr, ld, m0 + nt * BB + q * 256);
+        }
+      }
+      cnt += NE * WPB;
+    }
+  }
+  rec.m = (fl & 0x1ff) | ((uint32_t)cu.ph << 9) | (1u << 10) | ((uint32_t)cnt << 11) | ((uint32_t)cu.s << 16);
+  ivalid = next_step(cu, t, pre, tasks, t1);
+}
+
+// Stage-1 matrix work of k-groups J0, J0 + 1 on the first NC tiles of T:
+// x positions px, op(L) values lv (already scaled and masked).
+template <typename T, int NT, int NC, int K, int J0>
+__device__ __forceinline__ void stage1(typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm, const i4 px,
+                                       const typename Mfma<T>::v4 lv) {
+  const T* xs = sm.xs[K];
+#pragma unroll
+  for (int j = J0; j < J0 + 2; ++j) {
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) Tc[cc] = Mfma<T>::run(xs[cc * 256 + px[j]], lv[j], Tc[cc]);
+    // keep the operand reads of one k-group next to its matrix instructions
+    // (hoisting all of them raises the register peak past the budget)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+template <typename T, int NT, int NE, int CC, int K, int J0>
+__device__ __forceinline__ void stage2(typename Mfma<T>::v4 (&acc)[NT], const typename Mfma<T>::v4 (&Tc)[NT],
+                                       const Smem<T, NT>& sm, const i4 pr, int ok) {
+  const T* xs = sm.xs[K];
+#pragma unroll
+  for (int i = J0; i < J0 + 2; ++i) {
+    const T a = ((ok >> i) & 1) ? Tc[CC][i] : T(0);
+#pragma unroll
+    for (int nt = 0; nt < NE; ++nt) acc[nt] = Mfma<T>::run(a, xs[nt * 256 + pr[i]], acc[nt]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+template <typename T, int NT, int LO, int HI, int K, int J0>
+__device__ __forceinline__ void stage1_sw(int nc, typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm,
+                                          const i4 px, const typename Mfma<T>::v4 lv) {
+  if constexpr (LO == HI) {
+    stage1<T, NT, LO, K, J0>(Tc, sm, px, lv);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (nc <= MID) stage1_sw<T, NT, LO, MID, K, J0>(nc, Tc, sm, px, lv);
+    else stage1_sw<T, NT, MID + 1, HI, K, J0>(nc, Tc, sm, px, lv);
+  }
+}
+template <typename T, int NT, int NE, int LO, int HI, int K, int J0>
+__device__ __forceinline__ void stage2_sw(int s, typename Mfma<T>::v4 (&acc)[NT],
+                                          const typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm,
+                                          const i4 pr, int ok) {
+  if constexpr (LO == HI) {
+    stage2<T, NT, NE, LO, K, J0>(acc, Tc, sm, pr, ok);
+  } else {
+    constexpr int MID = (LO + HI) / 2;
+    if (s <= MID) stage2_sw<T, NT, NE, LO, MID, K, J0>(s, acc, Tc, sm, pr, ok);
+    else stage2_sw<T, NT, NE, MID + 1, HI, K, J0>(s, acc, Tc, sm, pr, ok);
+  }
+}
+
+// Matrix work of half H of the step recorded in rc (k-groups or T-column
+// groups 2H, 2H + 1), from ring slot K.
+template <typename T, int NT, int NE, int K, int H>
+__device__ __forceinline__ void compute(const Rec& rc, typename Mfma<T>::v4 (&Tc)[NT],
+                                        typename Mfma<T>::v4 (&acc)[NT], const Smem<T, NT>& sm, const LaneC<T>& lc,
+                                        int rabs, int wave) {
+  using v4 = typename Mfma<T>::v4;
+  const uint32_t fl = rc.flags();
+  const int rs = rc.s();
+  const int s16 = 16 * rs;
+  const int rb = rc.b(), rcc = rc.c();
+  if (rc.ph() == 0) {
+    if (H == 0 && rs == 0) {
+#pragma unroll
+      for (int cc = 0; cc < NT; ++cc) Tc[cc] = v4{0, 0, 0, 0};
+    }
+    const bool krx = !(fl & T_TX), krl = (fl & T_TL) != 0, idl = (fl & T_IDL) != 0;
+    const T f = (T)rc.f;
+    i4 px;
+    v4 lv;
+    const T* ls = sm.ls[K] + wave * 256;
+#pragma unroll
+    for (int j = 2 * H; j < 2 * H + 2; ++j) {
+      px[j] = krx ? 64 * j + lc.lane : lc.tp[j];
+      const int k = s16 + 4 * j + lc.g;
+      const T l = ls[krl ? 64 * j + lc.lane : lc.tp[j]];
+      lv[j] = idl ? (rabs == k ? f : T(0)) : (k < rb ? l * f : T(0));
+    }
+    stage1_sw<T, NT, 1, NT, K, 2 * H>(min(NT, (rcc + 15) >> 4), Tc, sm, px, lv);
+  } else {
+    const bool kr = !(fl & T_TR);
+    i4 pr;
+    int ok = 0;
+#pragma unroll
+    for (int i = 2 * H; i < 2 * H + 2; ++i) {
+      pr[i] = kr ? 64 * i + lc.lane : lc.tp[i];
+      ok |= (s16 + Mfma<T>::row(i, lc.g) < rcc ? 1 : 0) << i;
+    }
+    stage2_sw<T, NT, NE, 0, NT - 1, K, 2 * H>(rs, acc, Tc, sm, pr, ok);
+  }
+}
+
+// One pipeline iteration with compute slot K of an S-slot ring: wait for
+// the step's loads (all but those of the S - 2 steps issued after it),
+// barrier, first half of the matrix work, issue of the step S - 1 ahead
+// into the slot freed by the previous step (while the matrix instructions
+// of the first half execute), second half.
+template <typename T, int NT, int NE, int K>
+__device__ __forceinline__ bool iter(Ring<T, NT>& r, typename Mfma<T>::v4 (&Tc)[NT],
+                                     typename Mfma<T>::v4 (&acc)[NT], Smem<T, NT>& sm, const LaneC<T>& lc,
+                                     Cursor& cu, Task& t, Task& pre, bool& ivalid, const Task* __restrict__ tasks,
+                                     int t1, const Bases<T>& B, int row0, int wave, int rabs, bool wave_on) {
+  constexpr int S = Cfg<T, NT>::stages;
+  int pending = 0;
+#pragma unroll
+  for (int d = 1; d <= S - 2; ++d) pending += r[(K + d) % S].cnt();
+  wait_vm_le(pending);
+  lds_barrier();
+  if (!r[K].valid()) return false;
+  if (wave_on) compute<T, NT, NE, K, 0>(r[K], Tc, acc, sm, lc, rabs, wave);
+  __builtin_amdgcn_sched_barrier(0);
+  issue<T, NT, NE, (K + S - 1) % S>(r[(K + S - 1) % S], cu, t, pre, ivalid, tasks, t1, B, sm, lc, row0, wave);
+  __builtin_amdgcn_sched_barrier(0);
+  if (wave_on) compute<T, NT, NE, K, 1>(r[K], Tc, acc, sm, lc, rabs, wave);
+  return true;
+}
+// the S iterations of one turn of the ring; false once the tile is done
+template <typename T, int NT, int NE, int K>
+__device__ __forceinline__ bool turn(Ring<T, NT>& r, typename Mfma<T>::v4 (&Tc)[NT],
+                                     typename Mfma<T>::v4 (&acc)[NT], Smem<T, NT>& sm, const LaneC<T>& lc,
+                                     Cursor& cu, Task& t, Task& pre, bool& ivalid, const Task* __restrict__ tasks,
+                                     int t1, const Bases<T>& B, int row0, int wave, int rabs, bool wave_on) {
+  if constexpr (K == Cfg<T, NT>::stages) {
+    return true;
+  } else {
+    if (!iter<T, NT, NE, K>(r, Tc, acc, sm, lc, cu, t, pre, ivalid, tasks, t1, B, row0, wave, rabs, wave_on))
+      return false;
+    return turn<T, NT, NE, K + 1>(r, Tc, acc, sm, lc, cu, t, pre, ivalid, tasks, t1, B, row0, wave, rabs, wave_on);
+  }
+}
+template <typename T, int NT, int NE, int K>
+__device__ __forceinline__ void prologue(Ring<T, NT>& r, Smem<T, NT>& sm, const LaneC<T>& lc,
+                                         Cursor& cu, Task& t, Task& pre, bool& ivalid,
+                                         const Task* __restrict__ tasks, int t1, const Bases<T>& B, int row0,
+                                         int wave) {
+  if constexpr (K < Cfg<T, NT>::stages - 1) {
+    issue<T, NT, NE, K>(r[K], cu, t, pre, ivalid, tasks, t1, B, sm, lc, row0, wave);
+    prologue<T, NT, NE, K + 1>(r, sm, lc, cu, t, pre, ivalid, tasks, t1, B, row0, wave);
+  } else {
+    r[K].m = 0;
+  }
+}
+
+template <typename T, int NT, int NE>
+__device__ __forceinline__ void item_e(const Tile& tile, const Work& w, const Task* __restrict__ tasks,
+                                       const Bases<T>& B, Smem<T, NT>& sm) {
+  using M = Mfma<T>;
+  using v4 = typename M::v4;
+  const int tid = threadIdx.x;
+  const LaneC<T> lc(tid);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wrow0 = w.row0 + wave * 16;
+  const bool wave_on = wrow0 < tile.a;
+  const int rabs = wrow0 + lc.n;
+  v4 acc[NT], Tc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) acc[nt] = v4{0, 0, 0, 0};
+  if (tile.t0 < tile.t1) {
+    Cursor cu{tile.t0, 0, 0};
+    Task t = tasks[tile.t0];
+    Task pre = tasks[min(tile.t0 + 1, tile.t1 - 1)];
+    bool ivalid = true;
+    Ring<T, NT> r;
+    prologue<T, NT, NE, 0>(r, sm, lc, cu, t, pre, ivalid, tasks, tile.t1, B, w.row0, wave);
+    while (turn<T, NT, NE, 0>(r, Tc, acc, sm, lc, cu, t, pre, ivalid, tasks, tile.t1, B, w.row0, wave, rabs, wave_on)) {
+    }
+  }
+  wait_vm<0>();
+  if (!wave_on) return;
+  const int E = tile.e;
+#pragma unroll
+  for (int nt = 0; nt < NE; ++nt) {
+    const int col = nt * 16 + lc.n;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wrow0 + M::row(i, lc.g);
+      if (r < tile.a && col < E) B.out[tile.offOut + (int64_t)r * tile.ldOut + col] = acc[nt][i];
+    }
+  }
+}
+
+}  // namespace dmak
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256, (dmak::Cfg<T, NT>::groups)) void chain_dma(const Tile* __restrict__ tiles,
+                                                                         const Work* __restrict__ work,
+                                                                         const Task* __restrict__ tasks, Bases<T> B) {
+  static_assert(NT <= 8, "ring kernel covers output widths up to 128");
+  __shared__ dmak::Smem<T, NT> sm;
+  const Work w = work[blockIdx.x];
+  if (w.row0 < 0) return;  // unused position of the XCD-ordered list
+  const Tile tile = tiles[w.tile];
+  const int ne = (tile.e + 15) >> 4;
+  if (ne <= NeBucket<NT, 1>::value)
+    dmak::item_e<T, NT, NeBucket<NT, 1>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 2>::value)
+    dmak::item_e<T, NT, NeBucket<NT, 2>::value>(tile, w, tasks, B, sm);
+  else if (ne <= NeBucket<NT, 3>::value)
+    dmak::item_e<T, NT, NeBucket<NT, 3>::value>(tile, w, tasks, B, sm);
+  else
+    dmak::item_e<T, NT, NT>(tile, w, tasks, B, sm);
+}
+
 template <typename T>
 static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<T> b,
                                        const hipStream_t* ss, hipEvent_t (*ev)[2]) {
@@ -497,9 +947,20 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
     }
     dim3 grid((unsigned)ws.n[v]), blk(256);
     switch (v) {
-      case 0: hipLaunchKernelGGL((chain_mfma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
-      case 1: hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
-      case 2: hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      // FP64 up to 128 wide: LDS-ring kernel; FP32 and the 256-wide
+      // instance: register-staged kernel
+      case 0:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        else hipLaunchKernelGGL((chain_mfma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        break;
+      case 1:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        else hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        break;
+      case 2:
+        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        else hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        break;
       default: hipLaunchKernelGGL((chain_mfma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
     }
     hipError_t e = hipGetLastError();
