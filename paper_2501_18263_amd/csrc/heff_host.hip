@@ -596,6 +596,27 @@ struct DevWorkSet {
   }
 };
 
+// Readable element counts of the FP64 operand buffers (the ring kernel's
+// 16-byte loads stay inside them).
+static int64_t elems64(const DevBuf& d) { return (int64_t)(d.bytes / sizeof(double)); }
+static void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, const DevBuf& x0, const DevBuf& x1,
+                       const DevBuf& r0, const DevBuf& r1) {
+  b.lim[0] = elems64(l0);
+  b.lim[1] = elems64(l1);
+  b.lim[2] = elems64(x0);
+  b.lim[3] = elems64(x1);
+  b.lim[4] = elems64(r0);
+  b.lim[5] = elems64(r1);
+}
+static void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, int64_t x, const DevBuf& r0,
+                       const DevBuf& r1) {
+  b.lim[0] = elems64(l0);
+  b.lim[1] = elems64(l1);
+  b.lim[2] = b.lim[3] = x;
+  b.lim[4] = elems64(r0);
+  b.lim[5] = elems64(r1);
+}
+
 static void run_chain(ChainPlan& P, Bases<double> b, hipStream_t s) {
   if (P.tiles.empty()) return;
   split_large(P.tiles, P.tasks);
@@ -852,6 +873,7 @@ static std::unique_ptr<Block> grow_left(Block& old, const Bond& nb, const Iso& i
   b.X[0] = os.dev.as<double>();
   b.X[1] = lp.tmp.dev.as<double>();
   b.out = ns.dev.as<double>();
+  set_limits(b, iso.dev, iso.dev, os.dev, lp.tmp.dev, iso.dev, iso.dev);
   run_chain(P, b, s);
   return B;
 }
@@ -973,6 +995,7 @@ static std::unique_ptr<Block> grow_right(Block& old, const Bond& nb, const Iso& 
   b.X[0] = os.dev.as<double>();
   b.X[1] = lp.tmp.dev.as<double>();
   b.out = ns.dev.as<double>();
+  set_limits(b, iso.dev, iso.dev, os.dev, lp.tmp.dev, iso.dev, iso.dev);
   run_chain(P, b, s);
   return B;
 }
@@ -1602,6 +1625,7 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     bs.R[1] = b->Rtmp.tmp.dev.as<double>();
     bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
     bs.out = static_cast<double*>(out);
+    set_limits(bs, b->L->store.dev, b->Ltmp.tmp.dev, b->n_elem, b->R->store.dev, b->Rtmp.tmp.dev);
     hipStream_t vs[kNumVariants];
     fork_variants(ctx, vs);
     HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, vs, ev));

@@ -77,6 +77,11 @@ struct Bases {
   const T* X[2];
   const T* R[2];
   T* out;
+  // elements readable at L[0], L[1], X[0], X[1], R[0], R[1] (0: unknown).
+  // The FP64 ring kernel moves operand pairs with 16-byte loads, which may
+  // read one element past a block; it does so only where that element lies
+  // inside the buffer by these lengths, else it loads single dwords.
+  int64_t lim[6];
 };
 
 // Work items of the matrix-core kernels: kTileRows rows of one output block,

@@ -488,9 +488,13 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 // FP64, output widths up to 128.  Same work items, task order and
 // per-element arithmetic as chain_mfma (f folded into the op(L) value, the
 // same MFMA sequence; results are bitwise identical), but the operand slices
-// go straight from global memory to LDS with global_load_lds_dword: each
-// wave instruction moves one dword per lane into 256 consecutive LDS bytes
-// (LDS address = M0 + 4 lane; the global address is per lane).  No staging
+// go straight from global memory to LDS with global_load_lds_dwordx4: each
+// wave instruction moves 16 bytes (two consecutive elements of a stored row)
+// per lane into 1 KB of consecutive LDS (LDS address = M0 + 16 lane; the
+// global address is per lane and only needs 8-byte alignment).  Where a
+// pair could reach past the end of its buffer (buffer lengths unknown, or
+// the block is the buffer's last), the operand falls back to
+// global_load_lds_dword, one dword per lane into 256 bytes.  No staging
 // registers are needed, so the slices pass through a ring of three LDS
 // buffers: the loads of step s + 2 are in flight while step s computes,
 // which hides two steps of memory latency instead of one.  (For FP32, with
@@ -500,8 +504,10 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 // Every slice is held as 16 x 16 blocks of 256 elements.  Element (k, m) of
 // a block (k: contraction index of the step, m: row or column of the other
 // operand) sits at
-//   N  16 k + m          when the operand is stored with k as its row index,
-//   T  16 m + (k ^ m)    when it is stored with k contiguous.
+//   N  16 k + m               when the operand is stored with k as its row
+//                             index,
+//   T  16 m + (k ^ (m & 14))  when it is stored with k contiguous
+// (the XOR keeps the two elements of a 16-byte pair adjacent and in order).
 // Each layout puts one wave instruction's 256 bytes on 256 contiguous bytes
 // of global rows (a permutation inside them) and lets the 64 lanes of every
 // operand read hit distinct LDS banks (two lanes per bank pair, the minimum
@@ -540,6 +546,12 @@ __device__ __forceinline__ const char* sgpr_ptr(const char* p) {
 // LDS needs one wait state after the write of M0.
 __device__ __forceinline__ void dma(const char* sbase, uint32_t voff, uint32_t m0) {
   asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1" : : "v"(voff), "s"(sbase), "s"(m0)
+               : "memory");
+}
+// LDS[m0 + 16 lane, + 16) = the 16 bytes at sbase + voff (8-byte aligned)
+__device__ __forceinline__ void dma16(const char* sbase, uint32_t voff, uint32_t m0) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(sbase),
+               "s"(m0)
                : "memory");
 }
 template <int N>
@@ -593,16 +605,19 @@ struct Rec {
 template <typename T, int NT>
 using Ring = Rec[Cfg<T, NT>::stages];
 
-// Per-lane constants.  Lane l = 16 g + n.  In a 256-byte window q of a
-// block (32 elements, two dwords each) lane l writes dword l & 1 of element
-// 32 q + l / 2; its stored (row, column) is, for the N layout,
-// (k, m) = (2 q + y, mcol), for the T layout (m, k) = (2 q + y, cx ^ 2 q).
+// Per-lane constants.  Lane l = 16 g + n.
+//   16-byte loads: in 1 KB window q (0, 1) of a block lane l writes
+//   elements 128 q + 2 l, + 1, stored at (row, column) = (8 q + r8, c + d)
+//   (d = 0, 1) with r8 = l >> 3 and, for N, c = 2 (l & 7) (row = k), for T,
+//   c = (2 (l & 7) ^ ((l >> 3) & 6)) ^ 8 q (row = m, column = k).
+//   Dword loads: in 256-byte window q (0..7) lane l writes dword l & 1 of
+//   element 32 q + l / 2, stored at (row, column) = (2 q + y, mcol) for N and
+//   (2 q + y, mcol ^ 2 q) for T.
 typedef int i4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct LaneC {
-  static constexpr int A = 2;  // block rows per window
-  int lane, g, n, y, mcol, cx, h;
+  int lane, g, n, y, mcol, h, r8, cn, ct;
   i4 tp;  // T position of (k = 4j + g, m = n)
   __device__ __forceinline__ explicit LaneC(int tid) {
     lane = tid & 63;
@@ -611,9 +626,11 @@ struct LaneC {
     y = lane >> 5;
     mcol = (lane >> 1) & 15;
     h = lane & 1;
-    cx = mcol ^ y;
+    r8 = lane >> 3;
+    cn = 2 * (lane & 7);
+    ct = cn ^ (r8 & 6);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) tp[j] = 16 * n + ((4 * j + g) ^ n);
+    for (int j = 0; j < 4; ++j) tp[j] = 16 * n + ((4 * j + g) ^ (n & 14));
   }
 };
 
@@ -628,16 +645,74 @@ struct Span {
   }
 };
 
-// ring loads of one op(X)/op(L)-style window: element offset (rowi, z)
+// Ring loads of nb 16 x 16 blocks of one operand slice, block i starting at
+// element soff + i step of the stored block and landing at LDS m0 + i 2 KB;
+// the windows are shared out over the four waves.  Returns the loads this
+// wave issued.
 template <typename T>
-__device__ __forceinline__ void dma_window(const char* base, const Span& sp, const LaneC<T>& lc, int q, bool kr,
-                                           uint32_t ld, uint32_t m0) {
-  constexpr int A = LaneC<T>::A;
-  const uint32_t rowi = (uint32_t)(A * q + lc.y);
-  const uint32_t z = kr ? (uint32_t)lc.mcol : (uint32_t)(lc.cx ^ (A * q));
-  uint32_t off = rowi * ld + z;
-  off = off < sp.rel ? off : sp.rel;
-  dma(sgpr_ptr(base + (uint64_t)sp.sb * sizeof(T)), off * (uint32_t)sizeof(T) + 4u * lc.h, m0);
+__device__ __forceinline__ int load_blocks(const char* base, uint32_t soff, uint32_t step, uint32_t end, bool x4,
+                                           int nb, bool kr, uint32_t ld, uint32_t m0, const LaneC<T>& lc,
+                                           int wave) {
+  constexpr uint32_t BB = 256 * sizeof(T);
+  int cnt = 0;
+  if (x4) {
+    const uint32_t l0 = (uint32_t)lc.r8 * ld + (uint32_t)(kr ? lc.cn : lc.ct);
+    const uint32_t l1 = (uint32_t)(lc.r8 + 8) * ld + (uint32_t)(kr ? lc.cn : (lc.ct ^ 8));
+#pragma unroll 1
+    for (int v = wave; v < 2 * nb; v += 4) {
+      const int i = v >> 1;
+      const Span sp(soff + (uint32_t)i * step, end);
+      uint32_t off = (v & 1) ? l1 : l0;
+      off = off < sp.rel ? off : sp.rel;
+      dma16(sgpr_ptr(base + (uint64_t)sp.sb * sizeof(T)), off * (uint32_t)sizeof(T), m0 + i * BB + (v & 1) * 1024);
+      ++cnt;
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < nb; ++i) {
+      const Span sp(soff + (uint32_t)i * step, end);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int q = 2 * wave + u;
+        const uint32_t z = kr ? (uint32_t)lc.mcol : (uint32_t)(lc.mcol ^ (2 * q));
+        uint32_t off = (uint32_t)(2 * q + lc.y) * ld + z;
+        off = off < sp.rel ? off : sp.rel;
+        dma(sgpr_ptr(base + (uint64_t)sp.sb * sizeof(T)), off * (uint32_t)sizeof(T) + 4u * lc.h,
+            m0 + i * BB + q * 256);
+      }
+      cnt += 2;
+    }
+  }
+  return cnt;
+}
+// Ring loads of one whole block by this wave (its op(L) rows).
+template <typename T>
+__device__ __forceinline__ int load_own_block(const char* base, const Span& sp, bool x4, bool kr, uint32_t ld,
+                                              uint32_t m0, const LaneC<T>& lc) {
+  const char* sb = sgpr_ptr(base + (uint64_t)sp.sb * sizeof(T));
+  if (x4) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      uint32_t off = (uint32_t)(lc.r8 + 8 * q) * ld + (uint32_t)(kr ? lc.cn : (lc.ct ^ (8 * q)));
+      off = off < sp.rel ? off : sp.rel;
+      dma16(sb, off * (uint32_t)sizeof(T), m0 + q * 1024);
+    }
+    return 2;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t z = kr ? (uint32_t)lc.mcol : (uint32_t)(lc.mcol ^ (2 * q));
+    uint32_t off = (uint32_t)(2 * q + lc.y) * ld + z;
+    off = off < sp.rel ? off : sp.rel;
+    dma(sb, off * (uint32_t)sizeof(T) + 4u * lc.h, m0 + q * 256);
+  }
+  return 8;
+}
+// whether a 16-byte pair starting at any element of a stored block (at
+// element offset off, last element end) stays inside a buffer of lim
+// elements
+__device__ __forceinline__ bool pairs_fit(int64_t off, uint32_t end, int64_t lim) {
+  return off + (int64_t)end + 1 < lim;
 }
 
 // Issue the ring loads of the step at cursor (cu, t) into slot KI and fill
@@ -646,9 +721,6 @@ template <typename T, int NT, int NE, int KI>
 __device__ __forceinline__ void issue(Rec& rec, Cursor& cu, Task& t, Task& pre, bool& ivalid,
                                       const Task* __restrict__ tasks, int t1, const Bases<T>& B, Smem<T, NT>& sm,
                                       const LaneC<T>& lc, int row0, int wave) {
-  constexpr int WPB = sizeof(T) / 4;  // windows of one block per wave
-  constexpr int LW = sizeof(T);       // windows of one op(L) block
-  constexpr int BB = 256 * sizeof(T); // bytes of one block
   if (!ivalid) {
     rec.m = 0;
     return;
@@ -664,66 +736,47 @@ __device__ __forceinline__ void issue(Rec& rec, Cursor& cu, Task& t, Task& pre, 
     const bool kr = !(fl & T_TX);
     if (fl & T_IDX) {
       const int E = tid;
-      const int k = kr ? (E >> 4) : ((E & 15) ^ (E >> 4));
+      const int k = kr ? (E >> 4) : ((E & 15) ^ ((E >> 4) & 14));
       const int m = kr ? (E & 15) : (E >> 4);
 #pragma unroll
       for (int cc = 0; cc < NT; ++cc)
         if (cc < nc) sm.xs[KI][cc * 256 + E] = T(s16 + k == 16 * cc + m ? 1 : 0);
     } else {
       const uint32_t ld = t.ldX;
-      const char* xb = (const char*)(pick((fl & T_SELX) != 0, B.X[0], B.X[1]) + t.offX);
+      const int sel = (fl & T_SELX) != 0;
+      const char* xb = (const char*)(pick(sel, B.X[0], B.X[1]) + t.offX);
       const uint32_t end = kr ? (uint32_t)(t.b - 1) * ld + (t.c - 1) : (uint32_t)(t.c - 1) * ld + (t.b - 1);
-      const uint32_t step = kr ? 16u : 16u * ld;
-      uint32_t sb0 = kr ? (uint32_t)s16 * ld : (uint32_t)s16;
-      const uint32_t m0 = lds_addr(&sm.xs[KI][0]);
-#pragma unroll 1
-      for (int cc = 0; cc < nc; ++cc, sb0 += step) {
-        const Span sp(sb0, end);
-#pragma unroll
-        for (int u = 0; u < WPB; ++u) {
-          const int q = wave * WPB + u;
-          dma_window<T>(xb, sp, lc, q, kr, ld, m0 + cc * BB + q * 256);
-        }
-      }
-      cnt += nc * WPB;
+      cnt += load_blocks<T>(xb, kr ? (uint32_t)s16 * ld : (uint32_t)s16, kr ? 16u : 16u * ld, end,
+                            pairs_fit(t.offX, end, sel ? B.lim[3] : B.lim[2]), nc, kr, ld, lds_addr(&sm.xs[KI][0]),
+                            lc, wave);
     }
     if (!(fl & T_IDL)) {
-      const bool kr = (fl & T_TL) != 0;
+      const bool klr = (fl & T_TL) != 0;
       const uint32_t ld = t.ldL;
-      const char* lb = (const char*)(pick((fl & T_SELL) != 0, B.L[0], B.L[1]) + t.offL);
+      const int sel = (fl & T_SELL) != 0;
+      const char* lb = (const char*)(pick(sel, B.L[0], B.L[1]) + t.offL);
       const int r0 = row0 + 16 * wave;
-      const uint32_t end = kr ? (uint32_t)(t.b - 1) * ld + (t.a - 1) : (uint32_t)(t.a - 1) * ld + (t.b - 1);
-      const Span sp(kr ? (uint32_t)s16 * ld + r0 : (uint32_t)r0 * ld + s16, end);
-      const uint32_t m0 = lds_addr(&sm.ls[KI][wave * 256]);
-#pragma unroll
-      for (int q = 0; q < LW; ++q) dma_window<T>(lb, sp, lc, q, kr, ld, m0 + q * 256);
-      cnt += LW;
+      const uint32_t end = klr ? (uint32_t)(t.b - 1) * ld + (t.a - 1) : (uint32_t)(t.a - 1) * ld + (t.b - 1);
+      const Span sp(klr ? (uint32_t)s16 * ld + r0 : (uint32_t)r0 * ld + s16, end);
+      cnt += load_own_block<T>(lb, sp, pairs_fit(t.offL, end, sel ? B.lim[1] : B.lim[0]), klr, ld,
+                               lds_addr(&sm.ls[KI][wave * 256]), lc);
     }
   } else {
     const bool kr = !(fl & T_TR);
     if (fl & T_IDR) {
       const int E = tid;
-      const int j = kr ? (E >> 4) : ((E & 15) ^ (E >> 4));
+      const int j = kr ? (E >> 4) : ((E & 15) ^ ((E >> 4) & 14));
       const int col = kr ? (E & 15) : (E >> 4);
 #pragma unroll
       for (int nt = 0; nt < NE; ++nt) sm.xs[KI][nt * 256 + E] = T(s16 + j == 16 * nt + col ? 1 : 0);
     } else {
       const uint32_t ld = t.ldR;
-      const char* rb = (const char*)(pick((fl & T_SELR) != 0, B.R[0], B.R[1]) + t.offR);
+      const int sel = (fl & T_SELR) != 0;
+      const char* rb = (const char*)(pick(sel, B.R[0], B.R[1]) + t.offR);
       const uint32_t end = kr ? (uint32_t)(t.c - 1) * ld + (t.e - 1) : (uint32_t)(t.e - 1) * ld + (t.c - 1);
-      const uint32_t step = kr ? 16u : 16u * ld;
-      uint32_t sb0 = kr ? (uint32_t)s16 * ld : (uint32_t)s16;
-      const uint32_t m0 = lds_addr(&sm.xs[KI][0]);
-#pragma unroll 1
-      for (int nt = 0; nt < NE; ++nt, sb0 += step) {
-        const Span sp(sb0, end);
-#pragma unroll
-        for (int u = 0; u < WPB; ++u) {
-          const int q = wave * WPB + u;
-          dma_window<T>(rb, sp, lc, q, kr, ld, m0 + nt * BB + q * 256);
-        }
-      }
-      cnt += NE * WPB;
+      cnt += load_blocks<T>(rb, kr ? (uint32_t)s16 * ld : (uint32_t)s16, kr ? 16u : 16u * ld, end,
+                            pairs_fit(t.offR, end, sel ? B.lim[5] : B.lim[4]), NE, kr, ld, lds_addr(&sm.xs[KI][0]),
+                            lc, wave);
     }
   }
   rec.m = (fl & 0x1ff) | ((uint32_t)cu.ph << 9) | (1u << 10) | ((uint32_t)cnt << 11) | ((uint32_t)cu.s << 16);
@@ -734,10 +787,11 @@ __device__ __forceinline__ void issue(Rec& rec, Cursor& cu, Task& t, Task& pre, 
 // x positions px, op(L) values lv (already scaled and masked).
 template <typename T, int NT, int NC, int K, int J0>
 __device__ __forceinline__ void stage1(typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm, const i4 px,
-                                       const typename Mfma<T>::v4 lv) {
+                                       const typename Mfma<T>::v4 lv, int klim) {
   const T* xs = sm.xs[K];
 #pragma unroll
   for (int j = J0; j < J0 + 2; ++j) {
+    if (j > 0 && 4 * j >= klim) break;  // k-group past b: adds only zeros
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) Tc[cc] = Mfma<T>::run(xs[cc * 256 + px[j]], lv[j], Tc[cc]);
     // keep the operand reads of one k-group next to its matrix instructions
@@ -747,10 +801,11 @@ __device__ __forceinline__ void stage1(typename Mfma<T>::v4 (&Tc)[NT], const Sme
 }
 template <typename T, int NT, int NE, int CC, int K, int J0>
 __device__ __forceinline__ void stage2(typename Mfma<T>::v4 (&acc)[NT], const typename Mfma<T>::v4 (&Tc)[NT],
-                                       const Smem<T, NT>& sm, const i4 pr, int ok) {
+                                       const Smem<T, NT>& sm, const i4 pr, int ok, int jlim) {
   const T* xs = sm.xs[K];
 #pragma unroll
   for (int i = J0; i < J0 + 2; ++i) {
+    if (i > 0 && Mfma<T>::kmin(i) >= jlim) break;  // rows j past c: adds only zeros
     const T a = ((ok >> i) & 1) ? Tc[CC][i] : T(0);
 #pragma unroll
     for (int nt = 0; nt < NE; ++nt) acc[nt] = Mfma<T>::run(a, xs[nt * 256 + pr[i]], acc[nt]);
@@ -759,25 +814,25 @@ __device__ __forceinline__ void stage2(typename Mfma<T>::v4 (&acc)[NT], const ty
 }
 template <typename T, int NT, int LO, int HI, int K, int J0>
 __device__ __forceinline__ void stage1_sw(int nc, typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm,
-                                          const i4 px, const typename Mfma<T>::v4 lv) {
+                                          const i4 px, const typename Mfma<T>::v4 lv, int klim) {
   if constexpr (LO == HI) {
-    stage1<T, NT, LO, K, J0>(Tc, sm, px, lv);
+    stage1<T, NT, LO, K, J0>(Tc, sm, px, lv, klim);
   } else {
     constexpr int MID = (LO + HI) / 2;
-    if (nc <= MID) stage1_sw<T, NT, LO, MID, K, J0>(nc, Tc, sm, px, lv);
-    else stage1_sw<T, NT, MID + 1, HI, K, J0>(nc, Tc, sm, px, lv);
+    if (nc <= MID) stage1_sw<T, NT, LO, MID, K, J0>(nc, Tc, sm, px, lv, klim);
+    else stage1_sw<T, NT, MID + 1, HI, K, J0>(nc, Tc, sm, px, lv, klim);
   }
 }
 template <typename T, int NT, int NE, int LO, int HI, int K, int J0>
 __device__ __forceinline__ void stage2_sw(int s, typename Mfma<T>::v4 (&acc)[NT],
                                           const typename Mfma<T>::v4 (&Tc)[NT], const Smem<T, NT>& sm,
-                                          const i4 pr, int ok) {
+                                          const i4 pr, int ok, int jlim) {
   if constexpr (LO == HI) {
-    stage2<T, NT, NE, LO, K, J0>(acc, Tc, sm, pr, ok);
+    stage2<T, NT, NE, LO, K, J0>(acc, Tc, sm, pr, ok, jlim);
   } else {
     constexpr int MID = (LO + HI) / 2;
-    if (s <= MID) stage2_sw<T, NT, NE, LO, MID, K, J0>(s, acc, Tc, sm, pr, ok);
-    else stage2_sw<T, NT, NE, MID + 1, HI, K, J0>(s, acc, Tc, sm, pr, ok);
+    if (s <= MID) stage2_sw<T, NT, NE, LO, MID, K, J0>(s, acc, Tc, sm, pr, ok, jlim);
+    else stage2_sw<T, NT, NE, MID + 1, HI, K, J0>(s, acc, Tc, sm, pr, ok, jlim);
   }
 }
 
@@ -809,7 +864,7 @@ __device__ __forceinline__ void compute(const Rec& rc, typename Mfma<T>::v4 (&Tc
       const T l = ls[krl ? 64 * j + lc.lane : lc.tp[j]];
       lv[j] = idl ? (rabs == k ? f : T(0)) : (k < rb ? l * f : T(0));
     }
-    stage1_sw<T, NT, 1, NT, K, 2 * H>(min(NT, (rcc + 15) >> 4), Tc, sm, px, lv);
+    stage1_sw<T, NT, 1, NT, K, 2 * H>(min(NT, (rcc + 15) >> 4), Tc, sm, px, lv, rb - s16);
   } else {
     const bool kr = !(fl & T_TR);
     i4 pr;
@@ -819,7 +874,7 @@ __device__ __forceinline__ void compute(const Rec& rc, typename Mfma<T>::v4 (&Tc
       pr[i] = kr ? 64 * i + lc.lane : lc.tp[i];
       ok |= (s16 + Mfma<T>::row(i, lc.g) < rcc ? 1 : 0) << i;
     }
-    stage2_sw<T, NT, NE, 0, NT - 1, K, 2 * H>(rs, acc, Tc, sm, pr, ok);
+    stage2_sw<T, NT, NE, 0, NT - 1, K, 2 * H>(rs, acc, Tc, sm, pr, ok, rcc - s16);
   }
 }
 
