@@ -217,6 +217,20 @@ int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int prec, const vo
 int heff_op_arena(const heff_blocks* b, int prec, void* ptr[4], int64_t n_elem[4]);
 int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
                         const int32_t* pairs, double* g);
+/* heff_integral_gradient(): the derivatives of E = <psi|H_eff|psi> with
+ * respect to the one- and two-electron integrals of Eq. Hamiltonian_QC
+ * (psi: device, FP64, n_elem of p's two-site layout; isometries of p and
+ * psi held fixed), as symmetric tensors on the space of real symmetric
+ * integrals: for a symmetric change (dh, dV) of the integrals E changes by
+ * sum dh gh + sum dV gV.  gh (host, n_orb^2, row-major) is the spin-summed
+ * one-particle density matrix of the two-site state, gV (host, n_orb^4,
+ * (ij|kl) order) half its two-particle density matrix averaged over the
+ * eightfold index symmetry; either may be NULL to skip it.  E is linear in
+ * the integrals, so every orbit of indices costs one block build and one
+ * product: n_orb (n_orb + 1) / 2 for gh and about n_orb^4 / 8 for gV
+ * (exact; meant for small orbital counts).  Synchronizes the stream.
+ * Errors: HEFF_EINVAL (null problem or psi, integrals not symmetric). */
+int heff_integral_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, double* gh, double* gV);
 
 /* Davidson eigensolver for the lowest eigenpair of H_eff (the Diag_H step).
  * m_max in [3, 29] basis vectors, restart to {Ritz vector, previous Ritz

@@ -2412,6 +2412,65 @@ extern "C" int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int pre
   ABI_END(ctx)
 }
 
+// dE/dh and dE/dV of E = <psi|H_eff(h, V)|psi> (isometries and psi fixed),
+// as symmetric tensors.  E is linear in the integrals, so each component is
+// an energy: E with the indicator of one symmetry orbit of indices as the
+// integrals equals the orbit size times the common component.
+extern "C" int heff_integral_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, double* gh,
+                                      double* gV) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!p || !psi) throw Error(HEFF_EINVAL, "null argument");
+  Ints I;
+  validate_ints(p, I);
+  const int n = p->n_orb;
+  const size_t n2 = (size_t)n * n;
+  std::vector<double> dh(n2, 0.0), dV(n2 * n2, 0.0);
+  auto energy_at = [&](double* e) {
+    heff_problem q = *p;
+    q.h = dh.data();
+    q.V = dV.data();
+    heff_blocks* bq = nullptr;
+    int rc = heff_build_blocks(ctx, &q, 0u, &bq);
+    if (rc != HEFF_OK) return rc;
+    rc = heff_energy(ctx, bq, HEFF_FP64, psi, e);
+    heff_blocks_free(bq);
+    return rc;
+  };
+  if (gh) {
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) {
+        dh[(size_t)i * n + j] = dh[(size_t)j * n + i] = 1.0;
+        double e = 0.0;
+        const int rc = energy_at(&e);
+        dh[(size_t)i * n + j] = dh[(size_t)j * n + i] = 0.0;
+        if (rc != HEFF_OK) return rc;
+        gh[(size_t)i * n + j] = gh[(size_t)j * n + i] = i == j ? e : 0.5 * e;
+      }
+  }
+  if (gV) {
+    auto at = [&](int i, int j, int k, int l) { return ((size_t)(i * n + j) * n + k) * n + l; };
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j)
+        for (int k = 0; k <= i; ++k)
+          for (int l = 0; l <= (k == i ? j : k); ++l) {
+            // orbit of (ij|kl): pairs unordered, the two pairs exchangeable
+            const size_t m[8] = {at(i, j, k, l), at(j, i, k, l), at(i, j, l, k), at(j, i, l, k),
+                                 at(k, l, i, j), at(l, k, i, j), at(k, l, j, i), at(l, k, j, i)};
+            std::vector<size_t> orb(m, m + 8);
+            std::sort(orb.begin(), orb.end());
+            orb.erase(std::unique(orb.begin(), orb.end()), orb.end());
+            for (size_t x : orb) dV[x] = 1.0;
+            double e = 0.0;
+            const int rc = energy_at(&e);
+            for (size_t x : orb) dV[x] = 0.0;
+            if (rc != HEFF_OK) return rc;
+            for (size_t x : orb) gV[x] = e / (double)orb.size();
+          }
+  }
+  ABI_END(ctx)
+}
+
 extern "C" int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
                                    const int32_t* pairs, double* g) {
   if (!ctx) return HEFF_EINVAL;

@@ -79,6 +79,8 @@ _lib.heff_energy_backward.argtypes = [_vp, _vp, _i, _vp, ctypes.c_double, _vp, _
 _lib.heff_op_arena.argtypes = [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_kappa_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+_lib.heff_integral_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
 _lib.heff_batch_io.argtypes = [_vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_stats.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int64)]
@@ -91,7 +93,7 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
             "heff_task_stats_variant", "heff_task_stats_issued", "heff_energy", "heff_energy_backward",
-            "heff_op_arena", "heff_kappa_gradient", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_op_arena", "heff_kappa_gradient", "heff_integral_gradient", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
@@ -481,6 +483,24 @@ def kappa_gradient(ctx: Context, problem, psi, pairs):
                                        pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return g
+
+
+def integral_gradient(ctx: Context, problem, psi, one_body=True, two_body=True):
+    """(dE/dh, dE/dV) of E = <psi|H_eff|psi> (psi: float64 device tensor;
+    isometries and psi fixed) as symmetric tensors: the spin-summed
+    one-particle density matrix and half the symmetrized two-particle one of
+    the two-site state.  Exact; one block build and one product per
+    symmetry orbit of integral indices (small orbital counts)."""
+    keep = []
+    prob = _marshal(problem, keep)
+    n = problem.n_orb
+    gh = np.zeros((n, n)) if one_body else None
+    gV = np.zeros((n,) * 4) if two_body else None
+    dp = ctypes.POINTER(ctypes.c_double)
+    ctx.check(_lib.heff_integral_gradient(ctx._h, ctypes.byref(prob), _ptr(psi),
+                                          gh.ctypes.data_as(dp) if gh is not None else None,
+                                          gV.ctypes.data_as(dp) if gV is not None else None))
+    return gh, gV
 
 
 def _energy_function():

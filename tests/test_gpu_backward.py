@@ -150,3 +150,31 @@ def test_kappa_gradient_central_differences_n16(heff, ctx):
             Bq.close()
         fd = (es[0] - es[1]) / (2 * eps)
         assert abs(fd - gab) <= 1e-7, (a, b, fd, gab)
+
+
+def test_integral_gradient_matches_oracle_n4(heff, ctx):
+    # N=4 with every sector kept: the two-site state is a general state of
+    # the Fock sector; gh and gV against the oracle's FCI-based ones
+    p = synth.make_problem(4, 400, 3)
+    print("case integral gradient N=4 full seed=3", flush=True)
+    psi = np.random.default_rng(5).standard_normal(synth.psi_size(p))
+    gh, gV = heff.integral_gradient(ctx, p, _dev(psi))
+    rh, rV = grad.integral_gradient(p, psi)
+    scale = max(1.0, np.abs(rh).max())
+    assert np.abs(gh - rh).max() <= 1e-10 * scale
+    assert np.abs(gV - rV).max() <= 1e-10 * scale
+    # Euler relation against the device energy (E linear in the integrals)
+    B = heff.Blocks(ctx, p)
+    e = B.energy(_dev(psi))
+    B.close()
+    assert abs(np.sum(gh * p.h) + np.sum(gV * p.V) - e) <= 1e-10 * max(1.0, abs(e))
+
+
+def test_integral_gradient_one_body_n6(heff, ctx):
+    p = synth.make_problem(6, 400, 5)
+    print("case integral gradient N=6 full one-body seed=5", flush=True)
+    psi = np.random.default_rng(7).standard_normal(synth.psi_size(p))
+    gh, gV = heff.integral_gradient(ctx, p, _dev(psi), two_body=False)
+    assert gV is None
+    ref = grad.one_rdm(p, psi)
+    assert np.abs(gh - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())

@@ -55,3 +55,48 @@ def test_one_body_gradient_is_the_generalized_fock_commutator(small):
     g = grad.kappa_gradient(p0, psi, pairs)
     ref = np.array([2 * (F[x, y] - F[y, x]) for x, y in pairs])
     assert np.abs(g - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+@pytest.fixture(scope="module")
+def small4():
+    # N=4 with every sector kept (the whole Fock sector), random state
+    p = synth.make_problem(4, 400, 3)
+    psi = np.random.default_rng(5).standard_normal(synth.psi_size(p))
+    return p, psi
+
+
+def test_v_orbits_partition_the_index_space():
+    n = 4
+    orbs = grad.v_orbits(n)
+    members = [q for o in orbs for q in o]
+    assert len(members) == n ** 4 and len(set(members)) == n ** 4
+    m = n * (n + 1) // 2
+    assert len(orbs) == m * (m + 1) // 2   # distinct (ij|kl) of real integrals
+    assert all(len(o) in (1, 2, 4, 8) for o in orbs)
+
+
+def test_integral_gradient_euler_relation(small4):
+    # E is linear (homogeneous of degree one) in the integrals
+    p, psi = small4
+    gh, gV = grad.integral_gradient(p, psi)
+    e = grad.energy(p, psi)
+    assert abs(np.sum(gh * p.h) + np.sum(gV * p.V) - e) <= 1e-10 * max(1.0, abs(e))
+
+
+def test_integral_gradient_density_matrix_identities(small4):
+    # trace gamma = N_e |Phi|^2; contracting the two-particle part over one
+    # index pair gives (N_e - 1)/2 gamma (the state has N_e electrons);
+    # gamma is symmetric positive semidefinite with eigenvalues <= 2 |Phi|^2
+    p, psi = small4
+    gh, gV = grad.integral_gradient(p, psi)
+    phi, _ = grad.state(p, psi)
+    nrm = float(phi @ phi)
+    ne = p.n_up + p.n_dn
+    assert abs(np.trace(gh) - ne * nrm) <= 1e-10 * ne * nrm
+    assert np.allclose(gh, gh.T, atol=1e-12 * nrm)
+    w = np.linalg.eigvalsh(gh)
+    assert w.min() >= -1e-10 * nrm and w.max() <= 2 * nrm * (1 + 1e-10)
+    contr = np.einsum("ijkk->ij", gV)
+    assert np.abs(contr - 0.5 * (ne - 1) * gh).max() <= 1e-10 * nrm
+    # the one-body part agrees with gamma read off at V = 0
+    assert np.abs(gh - grad.one_rdm(p, psi)).max() <= 1e-10 * nrm
