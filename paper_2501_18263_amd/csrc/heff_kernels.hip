@@ -1002,15 +1002,29 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
     }
     dim3 grid((unsigned)ws.n[v]), blk(256);
     switch (v) {
-      // FP64 up to 128 wide: LDS-ring kernel; FP32 and the 256-wide
-      // instance: register-staged kernel
+      // FP64 128 wide: LDS-ring kernel.  FP64 32 and 64 wide: the ring
+      // kernel while the 128-wide variant runs beside them (sharing the CUs
+      // with it they leave it more of the chip), else the register-staged
+      // kernel (alone, with few matrix instructions per step, it is faster:
+      // 16.0 vs 22.2 ms at N=24 D=1024).  FP32 and the 256-wide instance:
+      // register-staged kernel.
       case 0:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
-        else hipLaunchKernelGGL((chain_mfma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        if constexpr (sizeof(T) == 8) {
+          if (ws.n[2] > 0) {
+            hipLaunchKernelGGL((chain_dma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+            break;
+          }
+        }
+        hipLaunchKernelGGL((chain_mfma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
         break;
       case 1:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
-        else hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        if constexpr (sizeof(T) == 8) {
+          if (ws.n[2] > 0) {
+            hipLaunchKernelGGL((chain_dma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+            break;
+          }
+        }
+        hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
         break;
       case 2:
         if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
