@@ -99,8 +99,14 @@ struct WorkSet {
 // ev: optional [kNumVariants][2] start/stop events recorded around each launch
 // s[v]: stream of variant v (the variants touch disjoint outputs and may run
 // concurrently); the single-stream forms launch all variants on one stream
+// mode (FP64 only): which kernel family runs the variants up to 128 wide,
+// kFp64Auto (LDS ring for the 128-wide variant and, while it runs, for the
+// narrower ones; register staging otherwise), kFp64Staged (register staging
+// everywhere) or kFp64Ring (the ring for every width up to 128).  The
+// families give bitwise identical results.
+enum { kFp64Auto = 0, kFp64Staged = 1, kFp64Ring = 2 };
 hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
-                           const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
+                           const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr, int mode = kFp64Auto);
 hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
                            const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
 inline hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
@@ -171,4 +177,5 @@ struct heff_ctx {
   // and joined back into `stream` by events); created on first use
   hipStream_t vs[heff::kNumVariants] = {};
   hipEvent_t fork = nullptr, join[heff::kNumVariants] = {};
+  int fp64_kernel = heff::kFp64Auto;  // kernel family of the FP64 product
 };

@@ -991,7 +991,7 @@ __global__ __launch_bounds__(256, (dmak::Cfg<T, NT>::groups)) void chain_dma(con
 
 template <typename T>
 static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<T> b,
-                                       const hipStream_t* ss, hipEvent_t (*ev)[2]) {
+                                       const hipStream_t* ss, hipEvent_t (*ev)[2], int mode) {
   // largest blocks first: their work items are the longest
   for (int v = kNumVariants - 1; v >= 0; --v) {
     if (ws.n[v] <= 0) continue;
@@ -1007,10 +1007,10 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
       // with it they leave it more of the chip), else the register-staged
       // kernel (alone, with few matrix instructions per step, it is faster:
       // 16.0 vs 22.2 ms at N=24 D=1024).  FP32 and the 256-wide instance:
-      // register-staged kernel.
+      // register-staged kernel.  `mode` can force one FP64 family.
       case 0:
         if constexpr (sizeof(T) == 8) {
-          if (ws.n[2] > 0) {
+          if (mode == kFp64Ring || (mode == kFp64Auto && ws.n[2] > 0)) {
             hipLaunchKernelGGL((chain_dma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
             break;
           }
@@ -1019,7 +1019,7 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
         break;
       case 1:
         if constexpr (sizeof(T) == 8) {
-          if (ws.n[2] > 0) {
+          if (mode == kFp64Ring || (mode == kFp64Auto && ws.n[2] > 0)) {
             hipLaunchKernelGGL((chain_dma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
             break;
           }
@@ -1027,8 +1027,13 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
         hipLaunchKernelGGL((chain_mfma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
         break;
       case 2:
-        if constexpr (sizeof(T) == 8) hipLaunchKernelGGL((chain_dma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
-        else hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        if constexpr (sizeof(T) == 8) {
+          if (mode != kFp64Staged) {
+            hipLaunchKernelGGL((chain_dma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+            break;
+          }
+        }
+        hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
         break;
       default: hipLaunchKernelGGL((chain_mfma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
     }
@@ -1043,12 +1048,12 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
 }
 
 hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
-                           const hipStream_t* s, hipEvent_t (*ev)[2]) {
-  return launch_mfma_variants<double>(tiles, ws, tasks, b, s, ev);
+                           const hipStream_t* s, hipEvent_t (*ev)[2], int mode) {
+  return launch_mfma_variants<double>(tiles, ws, tasks, b, s, ev, mode);
 }
 hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
                            const hipStream_t* s, hipEvent_t (*ev)[2]) {
-  return launch_mfma_variants<float>(tiles, ws, tasks, b, s, ev);
+  return launch_mfma_variants<float>(tiles, ws, tasks, b, s, ev, kFp64Auto);
 }
 
 // ------------------------------------------------------------------ chained product, bf16 split

@@ -79,6 +79,7 @@ _lib.heff_energy_backward.argtypes = [_vp, _vp, _i, _vp, ctypes.c_double, _vp, _
 _lib.heff_op_arena.argtypes = [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_kappa_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+_lib.heff_set_fp64_kernel.argtypes = [_vp, ctypes.c_int32]
 _lib.heff_integral_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
 _lib.heff_batch_io.argtypes = [_vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)), ctypes.POINTER(ctypes.c_int64)]
@@ -93,10 +94,11 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
             "heff_task_stats_variant", "heff_task_stats_issued", "heff_energy", "heff_energy_backward",
-            "heff_op_arena", "heff_kappa_gradient", "heff_integral_gradient", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_op_arena", "heff_kappa_gradient", "heff_integral_gradient", "heff_set_fp64_kernel", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
+FP64_AUTO, FP64_STAGED, FP64_RING = 0, 1, 2
 
 
 class HeffError(RuntimeError):
@@ -139,6 +141,11 @@ class Context:
         n = (ctypes.c_int64 * N_VARIANTS)()
         self.check(_lib.heff_timing_read(self._h, ms, n))
         return list(ms), list(n)
+
+    def set_fp64_kernel(self, mode):
+        """Kernel family of the FP64 products: FP64_AUTO, FP64_STAGED or
+        FP64_RING (bitwise identical results)."""
+        self.check(_lib.heff_set_fp64_kernel(self._h, int(mode)))
 
     def close(self):
         if getattr(self, "_h", None):

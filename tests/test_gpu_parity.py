@@ -277,3 +277,30 @@ def test_batch_matches_single_and_oracle(heff, ctx):
         y0 = block.apply(p, block.heff_terms(p), psi)
         assert np.linalg.norm(y.double().cpu().numpy() - y0) <= 1e-5 * np.linalg.norm(y0)
     bt.close()
+
+
+def test_fp64_kernel_families_agree_bitwise(heff, ctx):
+    # N=24, D=4096 has blocks wider than 64: the automatic choice runs the
+    # LDS-ring kernel; the register-staged kernel everywhere and the ring
+    # kernel everywhere must give the same product bit for bit (same sums in
+    # the same order), including the ring's dword fallback at buffer ends
+    p = synth.make_problem(24, 4096, 2)
+    print("case fp64 kernel families N=24 D=4096 seed=2", flush=True)
+    B = heff.Blocks(ctx, p)
+    st = B.variant_stats()
+    assert st[2][1] > 0  # a 128-wide variant exists
+    x = torch.tensor(synth.random_psi(p), device="cuda")
+    ys = []
+    try:
+        for mode in (heff.FP64_AUTO, heff.FP64_STAGED, heff.FP64_RING):
+            ctx.set_fp64_kernel(mode)
+            y = torch.empty_like(x)
+            B.apply(x, y)
+            ys.append(y.cpu().numpy())
+    finally:
+        ctx.set_fp64_kernel(heff.FP64_AUTO)
+    B.close()
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+    assert np.abs(ys[0]).max() > 0
+    with pytest.raises(heff.HeffError):
+        ctx.set_fp64_kernel(3)
