@@ -234,10 +234,10 @@ int heff_integral_gradient(heff_ctx* ctx, const heff_problem* p, const double* p
 
 /* heff_set_fp64_kernel(): which kernel family runs this context's FP64
  * products (heff_apply, heff_energy and the Davidson steps): 0 automatic
- * (the default: the LDS-ring kernel for blocks up to 128 wide when the
- * product has blocks wider than 64, else the register-staged kernel), 1 the
- * register-staged kernel for every width, 2 the ring kernel for every width
- * up to 128.  The families compute the same sums in the same order (bitwise
+ * (the default: the LDS-ring kernel when the product has blocks wider than
+ * 64, else the register-staged kernel), 1 the register-staged kernel for
+ * every width, 2 the ring kernel for every width.  The families compute
+ * the same sums in the same order (bitwise
  * identical results); the choice only moves time.  Errors: HEFF_EINVAL
  * (null context, mode outside 0..2). */
 int heff_set_fp64_kernel(heff_ctx* ctx, int32_t mode);

@@ -99,10 +99,10 @@ struct WorkSet {
 // ev: optional [kNumVariants][2] start/stop events recorded around each launch
 // s[v]: stream of variant v (the variants touch disjoint outputs and may run
 // concurrently); the single-stream forms launch all variants on one stream
-// mode (FP64 only): which kernel family runs the variants up to 128 wide,
-// kFp64Auto (LDS ring for the 128-wide variant and, while it runs, for the
-// narrower ones; register staging otherwise), kFp64Staged (register staging
-// everywhere) or kFp64Ring (the ring for every width up to 128).  The
+// mode (FP64 only): which kernel family runs the variants, kFp64Auto (LDS
+// ring for the 128- and 256-wide variants and, while one of them runs, for
+// the narrower ones; register staging otherwise), kFp64Staged (register
+// staging everywhere) or kFp64Ring (the ring for every width).  The
 // families give bitwise identical results.
 enum { kFp64Auto = 0, kFp64Staged = 1, kFp64Ring = 2 };
 hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,

@@ -485,7 +485,7 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 }
 
 // ------------------------------------------------------------------ chained product, LDS-DMA pipeline
-// FP64, output widths up to 128.  Same work items, task order and
+// FP64, all output widths.  Same work items, task order and
 // per-element arithmetic as chain_mfma (f folded into the op(L) value, the
 // same MFMA sequence; results are bitwise identical), but the operand slices
 // go straight from global memory to LDS with global_load_lds_dwordx4: each
@@ -520,16 +520,20 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 namespace dmak {
 
 
-// Ring depth and work-groups per CU.  Two work-groups per CU (the other
-// group's matrix work fills this one's barrier and issue time) with a
-// three-slot ring measured faster than one work-group with a four-slot
-// ring.  The kernel must not spill: a spill reload waits for every
-// outstanding load of the wave, ring loads included.
+// Ring depth and work-groups per CU.  Up to 128 wide, two work-groups per
+// CU (the other group's matrix work fills this one's barrier and issue time)
+// with a three-slot ring measured faster than one work-group with a
+// four-slot ring; the kernel must not spill there (a spill reload waits for
+// every outstanding load of the wave, ring loads included).  The 256-wide
+// instance (two 256-wide FP64 register tiles) runs one work-group per CU
+// with 120 KB of ring; it spills a few registers and is still faster than
+// the register-staged kernel (1507 vs 1726 ms at N=40 D=4096 with the wider
+// sectors of beta = 1).
 template <typename T, int NT>
 struct Cfg {
   static_assert(sizeof(T) == 8, "ring kernel is the FP64 path");
   static constexpr int stages = 3;
-  static constexpr int groups = 2;
+  static constexpr int groups = NT <= 8 ? 2 : 1;
 };
 typedef __attribute__((address_space(3))) char lds_char;
 
@@ -973,7 +977,6 @@ template <typename T, int NT>
 __global__ __launch_bounds__(256, (dmak::Cfg<T, NT>::groups)) void chain_dma(const Tile* __restrict__ tiles,
                                                                          const Work* __restrict__ work,
                                                                          const Task* __restrict__ tasks, Bases<T> B) {
-  static_assert(NT <= 8, "ring kernel covers output widths up to 128");
   __shared__ dmak::Smem<T, NT> sm;
   const Work w = work[blockIdx.x];
   if (w.row0 < 0) return;  // unused position of the XCD-ordered list
@@ -1002,15 +1005,15 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
     }
     dim3 grid((unsigned)ws.n[v]), blk(256);
     switch (v) {
-      // FP64 128 wide: LDS-ring kernel.  FP64 32 and 64 wide: the ring
-      // kernel while the 128-wide variant runs beside them (sharing the CUs
+      // FP64 128 and 256 wide: LDS-ring kernel.  FP64 32 and 64 wide: the
+      // ring kernel while a wider variant runs beside them (sharing the CUs
       // with it they leave it more of the chip), else the register-staged
       // kernel (alone, with few matrix instructions per step, it is faster:
-      // 16.0 vs 22.2 ms at N=24 D=1024).  FP32 and the 256-wide instance:
-      // register-staged kernel.  `mode` can force one FP64 family.
+      // 16.0 vs 22.2 ms at N=24 D=1024).  FP32: register-staged kernel.
+      // `mode` can force one FP64 family.
       case 0:
         if constexpr (sizeof(T) == 8) {
-          if (mode == kFp64Ring || (mode == kFp64Auto && ws.n[2] > 0)) {
+          if (mode == kFp64Ring || (mode == kFp64Auto && (ws.n[2] > 0 || ws.n[3] > 0))) {
             hipLaunchKernelGGL((chain_dma<T, 2>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
             break;
           }
@@ -1019,7 +1022,7 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
         break;
       case 1:
         if constexpr (sizeof(T) == 8) {
-          if (mode == kFp64Ring || (mode == kFp64Auto && ws.n[2] > 0)) {
+          if (mode == kFp64Ring || (mode == kFp64Auto && (ws.n[2] > 0 || ws.n[3] > 0))) {
             hipLaunchKernelGGL((chain_dma<T, 4>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
             break;
           }
@@ -1035,7 +1038,15 @@ static hipError_t launch_mfma_variants(const Tile* tiles, const WorkSet& ws, con
         }
         hipLaunchKernelGGL((chain_mfma<T, 8>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
         break;
-      default: hipLaunchKernelGGL((chain_mfma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b); break;
+      default:
+        if constexpr (sizeof(T) == 8) {
+          if (mode != kFp64Staged) {
+            hipLaunchKernelGGL((chain_dma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+            break;
+          }
+        }
+        hipLaunchKernelGGL((chain_mfma<T, 16>), grid, blk, 0, s, tiles, ws.w[v], tasks, b);
+        break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -280,15 +280,16 @@ def test_batch_matches_single_and_oracle(heff, ctx):
 
 
 def test_fp64_kernel_families_agree_bitwise(heff, ctx):
-    # N=24, D=4096 has blocks wider than 64: the automatic choice runs the
-    # LDS-ring kernel; the register-staged kernel everywhere and the ring
-    # kernel everywhere must give the same product bit for bit (same sums in
-    # the same order), including the ring's dword fallback at buffer ends
+    # N=24, D=4096 has blocks up to 194 wide (the 128- and 256-wide
+    # variants): the automatic choice runs the LDS-ring kernel; the
+    # register-staged kernel everywhere and the ring kernel everywhere must
+    # give the same product bit for bit (same sums in the same order),
+    # including the ring's dword fallback at buffer ends
     p = synth.make_problem(24, 4096, 2)
     print("case fp64 kernel families N=24 D=4096 seed=2", flush=True)
     B = heff.Blocks(ctx, p)
     st = B.variant_stats()
-    assert st[2][1] > 0  # a 128-wide variant exists
+    assert st[2][1] > 0 and st[3][1] > 0  # 128- and 256-wide variants exist
     x = torch.tensor(synth.random_psi(p), device="cuda")
     ys = []
     try:
