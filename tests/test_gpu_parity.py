@@ -208,6 +208,54 @@ def test_det_isometries_sampled_rows_n24(heff, ctx, D):
     assert np.abs(y[idx] - ref).max() <= 1e-10 * scale
 
 
+
+def test_full_size_sampled_rows_n40_d4096(heff, ctx):
+    # The product's own full-size configuration (N=40, D=4096, seed 3,
+    # beta 0.5: the same sector tables, tiles, task list and kernel launches
+    # as the timed product, only the isometry values differ) with 0/1
+    # determinant isometries, so that each output entry is one row of H_FCI
+    # applied to psi, which the oracle evaluates entry by entry.  Entries are
+    # drawn per psi block, stratified by block width (so every kernel width
+    # class is hit), one random entry and the block's last (ragged-edge)
+    # entry per block.  FP32 and the bf16 split are held to 1e-4 in norm over
+    # the sample: unit roundoff (6e-8 FP32, 2^-16 per split product) times
+    # about the square root of the ~10^6-term accumulation of an output.
+    p = synth.make_problem(40, 4096, 3, iso_kind="det")
+    print("case full size N=40 D=4096 seed=3 det isometries", flush=True)
+    B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32, heff.BF16X3))
+    psi = synth.random_psi(p)
+    from oracle import detbasis
+    dets = detbasis.psi_determinants(p)
+    order = np.lexsort((dets[:, 0], dets[:, 1]))
+    basis, xs = dets[order], psi[order]
+    rng = np.random.default_rng(7)
+    blocks = synth.psi_blocks(p)
+    classes = [[], [], []]               # widths <= 32, <= 64, <= 128 (none wider here)
+    for (_, _, _, _, da, db, off) in blocks:
+        w = max(da, db)
+        classes[0 if w <= 32 else 1 if w <= 64 else 2].append((da, db, off))
+    idx = []
+    for cl in classes:
+        for j in rng.permutation(len(cl))[:32]:
+            da, db, off = cl[j]
+            idx += [off + int(rng.integers(da * db)), off + da * db - 1]
+    idx = np.unique(np.array(idx))
+    assert all(len(cl) > 0 for cl in classes)
+    ref = np.array([fci.row_dot(p.h, p.V, dets[i], basis, xs) for i in idx])
+    x = _dev(psi)
+    y = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.apply(x, y)
+    y = y.cpu().numpy()
+    scale = np.abs(ref).max()
+    assert np.abs(y[idx] - ref).max() <= 1e-10 * scale
+    for prec in (heff.FP32, heff.BF16X3):
+        y32 = torch.empty(B.n_elem, dtype=torch.float32, device="cuda")
+        B.apply(x.float(), y32, prec=prec)
+        ys = y32.double().cpu().numpy()[idx]
+        err = np.linalg.norm(ys - ref) / np.linalg.norm(ref)
+        print("prec", prec, "sampled rel err", err)
+        assert err <= 1e-4
+
 def _iso_blocks(tab, old_tab, flat):
     """Split the flat isometry of site k into {q: stacked matrix}."""
     out, off = {}, 0
