@@ -209,10 +209,11 @@ def test_det_isometries_sampled_rows_n24(heff, ctx, D):
 
 
 
-def test_full_size_sampled_rows_n40_d4096(heff, ctx):
-    # The product's own full-size configuration (N=40, D=4096, seed 3,
-    # beta 0.5: the same sector tables, tiles, task list and kernel launches
-    # as the timed product, only the isometry values differ) with 0/1
+@pytest.mark.parametrize("beta", [0.5, 1.0])
+def test_full_size_sampled_rows_n40_d4096(heff, ctx, beta):
+    # The product's own full-size configuration (N=40, D=4096, seed 3, beta
+    # 0.5 and 1: the same sector tables, tiles, task list and kernel launches
+    # as the timed products, only the isometry values differ) with 0/1
     # determinant isometries, so that each output entry is one row of H_FCI
     # applied to psi, which the oracle evaluates entry by entry.  Entries are
     # drawn per psi block, stratified by block width (so every kernel width
@@ -220,8 +221,8 @@ def test_full_size_sampled_rows_n40_d4096(heff, ctx):
     # entry per block.  FP32 and the bf16 split are held to 1e-4 in norm over
     # the sample: unit roundoff (6e-8 FP32, 2^-16 per split product) times
     # about the square root of the ~10^6-term accumulation of an output.
-    p = synth.make_problem(40, 4096, 3, iso_kind="det")
-    print("case full size N=40 D=4096 seed=3 det isometries", flush=True)
+    p = synth.make_problem(40, 4096, 3, beta=beta, iso_kind="det")
+    print("case full size N=40 D=4096 seed=3 beta=%g det isometries" % beta, flush=True)
     B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32, heff.BF16X3))
     psi = synth.random_psi(p)
     from oracle import detbasis
@@ -230,17 +231,19 @@ def test_full_size_sampled_rows_n40_d4096(heff, ctx):
     basis, xs = dets[order], psi[order]
     rng = np.random.default_rng(7)
     blocks = synth.psi_blocks(p)
-    classes = [[], [], []]               # widths <= 32, <= 64, <= 128 (none wider here)
+    classes = [[], [], [], []]           # widths <= 32, <= 64, <= 128, wider
     for (_, _, _, _, da, db, off) in blocks:
         w = max(da, db)
-        classes[0 if w <= 32 else 1 if w <= 64 else 2].append((da, db, off))
+        classes[0 if w <= 32 else 1 if w <= 64 else 2 if w <= 128 else 3].append((da, db, off))
+    # beta = 1 keeps wider sectors: blocks beyond 128 (the 256-wide kernels)
+    assert (len(classes[3]) > 0) == (beta == 1.0)
     idx = []
     for cl in classes:
         for j in rng.permutation(len(cl))[:32]:
             da, db, off = cl[j]
             idx += [off + int(rng.integers(da * db)), off + da * db - 1]
     idx = np.unique(np.array(idx))
-    assert all(len(cl) > 0 for cl in classes)
+    assert all(len(cl) > 0 for cl in classes[:3])
     ref = np.array([fci.row_dot(p.h, p.V, dets[i], basis, xs) for i in idx])
     x = _dev(psi)
     y = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
