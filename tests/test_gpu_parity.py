@@ -59,6 +59,37 @@ def test_apply_matches_oracle(heff, ctx, N, D, seed):
     assert np.abs(d.cpu().numpy() - d0).max() <= 1e-10 * np.abs(d0).max()
 
 
+
+# Degenerate problems: the smallest chain (N=4: one site on each side of the
+# two-site pair), bond dimension 1 and 2 (every sector one or two states),
+# one electron, a single spin-orbital hole pattern (all up electrons and one
+# down), the vacuum (H_eff = 0: every output block has an empty or all-zero
+# task list and must still be written) and full filling (one determinant).
+EDGE = [(4, 16, 3, None, None), (8, 1, 4, None, None), (8, 2, 4, None, None), (7, 8, 6, 1, 0),
+        (6, 16, 5, 6, 1), (6, 16, 7, 0, 0), (6, 16, 7, 6, 6)]
+
+
+@pytest.mark.parametrize("N,D,seed,n_up,n_dn", EDGE)
+def test_apply_degenerate_cases(heff, ctx, N, D, seed, n_up, n_dn):
+    print("case degenerate N=%d D=%d seed=%d n_up=%s n_dn=%s" % (N, D, seed, n_up, n_dn), flush=True)
+    p = synth.make_problem(N, D, seed, n_up=n_up, n_dn=n_dn)
+    B = heff.Blocks(ctx, p)
+    assert layout_matches(p, B.blocks)
+    psi = synth.random_psi(p)
+    terms = block.heff_terms(p)
+    y0 = block.apply(p, terms, psi)
+    out = torch.full((B.n_elem,), float("nan"), dtype=torch.float64, device="cuda")
+    B.apply(_dev(psi), out)
+    y = out.cpu().numpy()
+    if not np.any(y0):
+        assert np.array_equal(y, y0)
+    else:
+        _check_fp64(y, y0)
+    d = torch.full((B.n_elem,), float("nan"), dtype=torch.float64, device="cuda")
+    B.diag(d)
+    d0 = davidson.diagonal(p, terms)
+    assert np.abs(d.cpu().numpy() - d0).max() <= 1e-10 * max(np.abs(d0).max(), 1e-300)
+
 def test_renormalized_operators_match_oracle(heff, ctx):
     p = synth.make_problem(8, 16, 5)
     B = heff.Blocks(ctx, p)
