@@ -40,6 +40,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def kernel_name(head, v, vst):
+    """Product kernel that runs variant v in precision `head` under the
+    library's automatic choice: FP64 takes the LDS-ring kernel for the 128-
+    and 256-wide variants, and for the narrower ones when a wider variant
+    has work; FP32 the register-staged kernel; the bf16 split its own."""
+    nt = [2, 4, 8, 16][v]
+    if head == "fp64":
+        ring = v >= 2 or vst[2][0] > 0 or vst[3][0] > 0
+        return "%s<double, %d>" % ("chain_dma" if ring else "chain_mfma", nt)
+    if head == "bf16x3":
+        return "chain_b3<%d>" % nt
+    return "chain_mfma<float, %d>" % nt
+
+
 def measured_traffic(variant):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel
@@ -415,9 +429,8 @@ def main():
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[head],
             "traffic": measured_traffic(v) if head == "fp64" else None,
-            "kernel": "%s<%s, %d> variant %d (output width and task middle dimension <= %d)" % (
-                "chain_dma" if head == "fp64" and v <= 2 else "chain_mfma", "double" if head == "fp64" else "float",
-                [2, 4, 8, 16][v], v, [32, 64, 128, 256][v]),
+            "kernel": "%s variant %d (output width and task middle dimension <= %d)" % (
+                kernel_name(head, v, vst), v, [32, 64, 128, 256][v]),
             "flops_per_launch": vst[v][0], "avg_launch_ms": avg_s * 1e3,
             "mfma_flops_per_launch": ist[v][0], "mfma_issue_efficiency": vst[v][0] / max(ist[v][0], 1.0),
             "pipeline_steps_per_launch": ist[v][1], "pipeline_steps_longest_group": ist[v][2]}
