@@ -60,6 +60,36 @@ def test_apply_matches_oracle(heff, ctx, N, D, seed):
 
 
 
+
+def test_davidson_full_size_properties_n40_d4096(heff, ctx):
+    # Davidson steps at the timed configuration (N=40, D=4096, seed 3), where
+    # no oracle run is affordable, checked by what holds at any size: the
+    # lowest Ritz value of a growing subspace never increases (Rayleigh-Ritz,
+    # Cauchy interlacing), the Ritz vector's Rayleigh quotient under a fresh
+    # FP64 product equals the reported Ritz value, and the reported residual
+    # norm equals ||H u - theta u|| / ||u|| of that vector.
+    p = synth.make_problem(40, 4096, 3)
+    print("case davidson full size N=40 D=4096 seed=3", flush=True)
+    B = heff.Blocks(ctx, p)
+    x0 = _dev(synth.random_psi(p))
+    dav = heff.Davidson(B, x0, m_max=24, tol=1e-14)
+    ths = []
+    for _ in range(5):                   # no restart within m_max steps
+        th, rn = dav.step()
+        ths.append(th)
+    for a, b in zip(ths, ths[1:]):
+        assert b <= a + 1e-12 * abs(a)
+    assert ths[-1] < ths[0]
+    u = torch.empty_like(x0)
+    dav.ritz(u)
+    hu = torch.empty_like(u)
+    B.apply(u, hu)
+    un = float(u.norm())
+    rq = float(u @ hu) / un ** 2
+    assert abs(rq - ths[-1]) <= 1e-10 * abs(ths[-1])
+    r = float((hu - ths[-1] * u).norm()) / un
+    assert abs(r - rn) <= 1e-8 * abs(ths[-1])
+
 # Degenerate problems: the smallest chain (N=4: one site on each side of the
 # two-site pair), bond dimension 1 and 2 (every sector one or two states),
 # one electron, a single spin-orbital hole pattern (all up electrons and one
@@ -282,6 +312,13 @@ def test_full_size_sampled_rows_n40_d4096(heff, ctx, beta):
     y = y.cpu().numpy()
     scale = np.abs(ref).max()
     assert np.abs(y[idx] - ref).max() <= 1e-10 * scale
+    # diagonal: with 0/1 isometries each entry is a determinant's diagonal
+    # element of H_FCI (the row of a one-determinant basis)
+    dg = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
+    B.diag(dg)
+    dg = dg.cpu().numpy()
+    dref = np.array([fci.row_dot(p.h, p.V, dets[i], np.ascontiguousarray(dets[i:i + 1]), np.ones(1)) for i in idx])
+    assert np.abs(dg[idx] - dref).max() <= 1e-10 * np.abs(dref).max()
     for prec in (heff.FP32, heff.BF16X3):
         y32 = torch.empty(B.n_elem, dtype=torch.float32, device="cuda")
         B.apply(x.float(), y32, prec=prec)
