@@ -363,6 +363,34 @@ def test_truncation_matches_oracle(heff, ctx, N, D, keep, planted):
             assert np.abs(G @ G.T - Q @ Q.T).max() <= 1e-8
 
 
+
+def test_truncation_full_size_n40_d4096(heff, ctx):
+    # the truncation step at the timed configuration (N=40, D=4096, seed 3):
+    # 201 enlarged sectors up to 488 wide, keep D = 4096 states
+    from oracle import svd
+    p = synth.make_problem(40, 4096, 3)
+    print("case truncation full size N=40 D=4096 seed=3 keep=4096", flush=True)
+    psi = synth.random_psi(p)
+    B = heff.Blocks(ctx, p)
+    got = B.truncate(_dev(psi), 4096)
+    sing, disc, tab, iso = svd.truncate(p, psi, 4096)
+    assert got["tab"] == tab
+    assert np.abs(got["sing"] - sing).max() <= 1e-10
+    assert abs(got["discarded"] - disc) <= 1e-11
+    gi = _iso_blocks(tab, p.tab_L, got["iso_flat"])
+    mats = svd.sector_matrices(p, psi)
+    for q, Q in iso.items():
+        G = gi[q]
+        assert np.abs(G.T @ G - np.eye(G.shape[1])).max() <= 1e-10
+        # the kept subspace of a sector is unique when its last kept and
+        # first dropped singular values differ; every sector here has a gap
+        # above 6e-6 (eigenvalue gap of rho ~1e-7), so rounding of order
+        # 1e-15 moves the projector by far less than the 1e-6 allowed
+        sv = np.linalg.svd(mats[q][0], compute_uv=False)
+        d = Q.shape[1]
+        assert sv[d - 1] - (sv[d] if d < len(sv) else 0.0) > 1e-6
+        assert np.abs(G @ G.T - Q @ Q.T).max() <= 1e-6
+
 def test_batch_matches_single_and_oracle(heff, ctx):
     # uneven problems (odd N -> S_z = 1/2), one persistent graph-captured
     # launch; every problem equals its own single-problem FP32 product
