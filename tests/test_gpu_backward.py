@@ -89,6 +89,45 @@ def test_operand_gradients_are_exact_derivatives(heff, case8):
     assert checked >= 16
 
 
+
+def test_backward_full_size_n40_d4096(heff, ctx):
+    # the backward at the timed configuration (N=40, D=4096, seed 3), by
+    # what holds at any size: dE/dpsi = 2 H_eff psi (against the forward
+    # product), psi . dE/dpsi = 2E (homogeneity of degree two), and unit
+    # steps of single operand-arena entries change E by exactly the
+    # reported gradient (E is linear in each entry)
+    p = synth.make_problem(40, 4096, 3)
+    print("case backward full size N=40 D=4096 seed=3", flush=True)
+    B = heff.Blocks(ctx, p)
+    x = _dev(synth.random_psi(p))
+    hx = torch.empty_like(x)
+    B.apply(x, hx)
+    e0 = B.energy(x)
+    assert abs(e0 - float(x @ hx)) <= 1e-11 * abs(e0)
+    dpsi, dL, dR = B.energy_backward(x)
+    assert float((dpsi - 2 * hx).norm()) <= 1e-11 * float(hx.norm())
+    assert abs(float(x @ dpsi) - 2 * e0) <= 1e-10 * abs(e0)
+    views = B.op_arena(heff.FP64)
+    n = [v.numel() for v in views]
+    grads = [dL[:n[0]], dL[n[0]:n[0] + n[1]], dR[:n[2]], dR[n[2]:n[2] + n[3]]]
+    rng = np.random.default_rng(12)
+    checked = 0
+    for v, gv in zip(views, grads):
+        if v.numel() == 0:
+            continue
+        nz = torch.nonzero(gv).flatten().cpu().numpy()
+        for i in (rng.choice(nz, min(2, len(nz)), replace=False) if len(nz) else []):
+            i = int(i)
+            old = float(v[i].item())
+            v[i] = old + 1.0
+            e1 = B.energy(x)
+            v[i] = old
+            g = float(gv[i].item())
+            assert abs((e1 - e0) - g) <= 1e-10 * max(1.0, abs(e0)), (i, e1 - e0, g)
+            checked += 1
+    assert checked >= 4
+    assert B.energy(x) == e0
+
 def test_fp32_gradients_track_fp64(heff, case8):
     p, B, psi = case8
     print("case backward fp32 N=8 D=32 seed=5", flush=True)
