@@ -283,6 +283,53 @@ def bench_backward(args):
     print(json.dumps(res), flush=True)
 
 
+
+def bench_shards(args):
+    """One GPU's share of an output-block-sharded FP64 product (the design
+    for several GPUs, of which one GPU can show each rank's kernel time):
+    for every rank of --shards P, the product restricted to that rank's
+    output blocks, timed around a device-wide synchronization; the slowest
+    rank bounds the
+    product on P GPUs (before the all-gather of psi')."""
+    import torch
+
+    from paper_2501_18263_amd import heff, synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    p = synth.make_problem(args.n_orb, args.d, args.seed, beta=args.beta)
+    ctx = heff.Context(0)
+    B = heff.Blocks(ctx, p)
+    x = torch.tensor(synth.random_psi(p), device="cuda")
+    y = torch.empty_like(x)
+    F = B.stats()["flops"]
+
+    def timed():
+        B.apply(x, y)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):   # device-wide sync: the product runs on the library's streams
+            t0 = time.perf_counter()
+            B.apply(x, y)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return sorted(ts)[len(ts) // 2]
+    full_ms = timed()
+    ranks = []
+    for r in range(args.shards):
+        fl = B.shard(r, args.shards)
+        ms = timed()
+        ranks.append({"rank": r, "flops": fl, "ms": ms, "tflops": fl / ms / 1e9})
+        log("rank %d/%d: %.3f ms  %.2f TFLOP/s" % (r, args.shards, ms, fl / ms / 1e9))
+    B.shard(0, 1)
+    worst = max(q["ms"] for q in ranks)
+    out = {"metric": "FP64 product, slowest rank of %d output-block shards, N=%d D=%d" % (args.shards, args.n_orb, args.d),
+           "value": worst, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": worst,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "one GPU per rank of a %d-way output-block shard, N=%d D=%d beta=%g" % (
+               args.shards, args.n_orb, args.d, args.beta), "flops_per_product": F},
+           "full_product_ms": full_ms, "speedup_bound": full_ms / worst,
+           "flop_imbalance": max(q["flops"] for q in ranks) / (F / args.shards), "ranks": ranks}
+    print(json.dumps(out), flush=True)
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,7 +341,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precs", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "backward"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "backward", "shards"], default="single")
+    ap.add_argument("--shards", type=int, default=8)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--converge", type=int, default=0,
                     help="also run each precision's Davidson to convergence (at most this many steps) "
@@ -323,6 +371,9 @@ def main():
         sys.exit(3)
     if args.workload == "backward":
         bench_backward(args)
+        return
+    if args.workload == "shards":
+        bench_shards(args)
         return
 
     import numpy as np  # noqa: F401

@@ -135,6 +135,20 @@ int heff_task_stats_variant(const heff_blocks* b, int v, double* flops, int64_t*
  * and of its longest work-group (the critical path of the launch). */
 int heff_task_stats_issued(const heff_blocks* b, int v, double* mfma_flops, int64_t* steps, int64_t* max_steps);
 
+/* One GPU's share of the product for a product spread over nranks GPUs by
+ * output blocks (Sec. II.D, parallelization of the product over devices).
+ * Output blocks are assigned, largest algorithmic flops first, to the rank
+ * with the least flops so far; afterwards every product on `b` (heff_apply
+ * and what calls it: Davidson steps, energies, backward) writes only the
+ * output blocks of `rank` and leaves the other elements of `out` untouched,
+ * each block with the same task order, hence the same bits, as the full
+ * product.  rank in [0, nranks); nranks = 1 restores the full product.
+ * shard_flops (may be NULL) receives this rank's algorithmic flops per
+ * product.  heff_task_stats_variant() then reports the rank's work-groups;
+ * the flop statistics stay those of the full product.  Synchronizes the
+ * context stream; returns HEFF_EINVAL for a bad rank or nranks. */
+int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, int32_t nranks, double* shard_flops);
+
 /* out = H_eff psi.  psi, out: device arrays of n_elem elements of the
  * precision's storage type (double for FP64, float for FP32 and BF16X3);
  * they must not alias.  Asynchronous on the context stream. */

@@ -1596,6 +1596,55 @@ extern "C" int heff_task_stats(const heff_blocks* b, int64_t* n_tasks, double* f
   return HEFF_OK;
 }
 
+// One GPU's share of the product when the output blocks are spread over
+// nranks GPUs (Sec. II.D: the product is distributed over devices; here by
+// output blocks, so no reduction is needed and each block keeps its own
+// summation order).  Output blocks go, largest algorithmic work first, to
+// the rank with the least work so far; the product's work lists are rebuilt
+// from this rank's blocks in the same order and placement rules as the
+// full product (nranks = 1 restores exactly the full lists).
+extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, int32_t nranks, double* shard_flops) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || nranks < 1 || rank < 0 || rank >= nranks) throw Error(HEFF_EINVAL, "bad shard (rank, nranks)");
+  HCHECK(hipSetDevice(ctx->device));
+  const std::vector<Tile>& tiles = b->h_tiles;
+  const std::vector<Task>& tasks = b->h_tasks;
+  const int nb = (int)tiles.size();
+  std::vector<double> fl(nb, 0.0), rowfl(nb, 0.0);
+  for (int y = 0; y < nb; ++y)
+    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) {
+      fl[y] += task_flops(tasks[k]);
+      rowfl[y] += task_flops(tasks[k]) / std::max(1, tiles[y].a);
+    }
+  std::vector<int> byfl(nb);
+  for (int i = 0; i < nb; ++i) byfl[i] = i;
+  std::stable_sort(byfl.begin(), byfl.end(), [&](int x, int y) { return fl[x] > fl[y]; });
+  std::vector<double> load(nranks, 0.0);
+  std::vector<int> owner(nb, 0);
+  for (int y : byfl) {
+    int r = 0;
+    for (int j = 1; j < nranks; ++j)
+      if (load[j] < load[r]) r = j;
+    owner[y] = r;
+    load[r] += fl[y];
+  }
+  // the full product's block order (largest per-row work first), restricted
+  std::vector<int> order(nb);
+  for (int i = 0; i < nb; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rowfl[x] > rowfl[y]; });
+  std::vector<int> mine;
+  for (int y : order)
+    if (owner[y] == rank) mine.push_back(y);
+  std::vector<Work> lists[kNumVariants];
+  split_work(tiles, tasks, mine, lists);
+  HCHECK(hipStreamSynchronize(ctx->stream));  // no product still reads the old lists
+  b->mwork.upload_lists(lists, ctx->stream);
+  HCHECK(hipStreamSynchronize(ctx->stream));
+  if (shard_flops) *shard_flops = load[rank];
+  ABI_END(ctx)
+}
+
 extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
   if (!ctx) return HEFF_EINVAL;
   ABI_BEGIN

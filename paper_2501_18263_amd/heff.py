@@ -62,6 +62,7 @@ _lib.heff_dav_free.argtypes = [_vp]
 _lib.heff_timing.argtypes = [_vp, _i]
 _lib.heff_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_task_stats_variant.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+_lib.heff_blocks_shard.argtypes = [_vp, _vp, _i, _i, ctypes.POINTER(ctypes.c_double)]
 _lib.heff_task_stats_issued.argtypes = [_vp, _i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_truncate.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp)]
@@ -93,7 +94,7 @@ _lib.heff_debug_op.restype = ctypes.c_int64
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
-            "heff_task_stats_variant", "heff_task_stats_issued", "heff_energy", "heff_energy_backward",
+            "heff_task_stats_variant", "heff_task_stats_issued", "heff_blocks_shard", "heff_energy", "heff_energy_backward",
             "heff_op_arena", "heff_kappa_gradient", "heff_integral_gradient", "heff_set_fp64_kernel", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
@@ -234,6 +235,14 @@ class Blocks:
         by = (ctypes.c_double * 3)()
         self.ctx.check(_lib.heff_task_stats(self._h, ctypes.byref(nt), ctypes.byref(fl), by))
         return dict(n_tasks=nt.value, flops=fl.value, bytes={"fp64": by[0], "fp32": by[1], "bf16x3": by[2]})
+
+    def shard(self, rank, nranks):
+        """Restrict every later product to the output blocks of `rank` of
+        `nranks` (nranks = 1: the full product); returns the rank's
+        algorithmic flops per product."""
+        fl = ctypes.c_double()
+        self.ctx.check(_lib.heff_blocks_shard(self.ctx._h, self._h, int(rank), int(nranks), ctypes.byref(fl)))
+        return fl.value
 
     def variant_stats(self):
         """[(algorithmic flops per product, work-groups)] per kernel variant."""

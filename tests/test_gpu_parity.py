@@ -90,6 +90,40 @@ def test_davidson_full_size_properties_n40_d4096(heff, ctx):
     r = float((hu - ths[-1] * u).norm()) / un
     assert abs(r - rn) <= 1e-8 * abs(ths[-1])
 
+
+@pytest.mark.parametrize("N,D,seed,P", [(12, 96, 12, 3), (16, 256, 21, 4)])
+def test_shards_partition_the_product_bitwise(heff, ctx, N, D, seed, P):
+    # one GPU's share of an output-block-sharded product: the P shards write
+    # disjoint sets of whole output blocks whose union is the full product,
+    # bit for bit, and their flops add up to the product's
+    print("case shards N=%d D=%d seed=%d P=%d" % (N, D, seed, P), flush=True)
+    p = synth.make_problem(N, D, seed)
+    B = heff.Blocks(ctx, p)
+    x = _dev(synth.random_psi(p))
+    full = torch.empty_like(x)
+    B.apply(x, full)
+    acc = torch.full_like(x, float("nan"))
+    fls = []
+    for r in range(P):
+        fls.append(B.shard(r, P))
+        y = torch.full_like(x, float("nan"))
+        B.apply(x, y)
+        w = ~torch.isnan(y)
+        assert not (w & ~torch.isnan(acc)).any()
+        for (_, _, _, _, rows, cols, off) in B.blocks:   # whole blocks only
+            blk = w[off: off + rows * cols]
+            assert bool(blk.all()) or not bool(blk.any())
+        acc[w] = y[w]
+        assert torch.equal(y[w], full[w])
+    assert B.shard(0, 1) == pytest.approx(B.stats()["flops"], rel=1e-12)
+    assert sum(fls) == pytest.approx(B.stats()["flops"], rel=1e-12)
+    assert torch.equal(acc, full)
+    y = torch.empty_like(x)
+    B.apply(x, y)
+    assert torch.equal(y, full)
+    with pytest.raises(Exception):
+        B.shard(P, P)
+
 # Degenerate problems: the smallest chain (N=4: one site on each side of the
 # two-site pair), bond dimension 1 and 2 (every sector one or two states),
 # one electron, a single spin-orbital hole pattern (all up electrons and one
