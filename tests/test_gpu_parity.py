@@ -153,6 +153,16 @@ def test_apply_degenerate_cases(heff, ctx, N, D, seed, n_up, n_dn):
     B.diag(d)
     d0 = davidson.diagonal(p, terms)
     assert np.abs(d.cpu().numpy() - d0).max() <= 1e-10 * max(np.abs(d0).max(), 1e-300)
+    # the reduced-precision products on the same problem (vacuum: exactly 0)
+    for prec in (heff.FP32, heff.BF16X3):
+        B32 = heff.Blocks(ctx, p, precs=(heff.FP64, prec))
+        y32 = torch.full((B.n_elem,), float("nan"), dtype=torch.float32, device="cuda")
+        B32.apply(_dev(psi, torch.float32), y32, prec=prec)
+        y32 = y32.double().cpu().numpy()
+        if not np.any(y0):
+            assert np.array_equal(y32, y0)
+        else:
+            assert np.linalg.norm(y32 - y0) <= 1e-4 * np.linalg.norm(y0)
 
 def test_renormalized_operators_match_oracle(heff, ctx):
     p = synth.make_problem(8, 16, 5)
