@@ -69,6 +69,69 @@ def measured_traffic(variant):
     return t.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(folder, counter, name_part):
+    """Counter values per dispatch of kernels whose name contains name_part,
+    from the rocprofv3 --output-format csv counter files under folder."""
+    import csv
+    import glob
+    vals = []
+    for path in sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") == counter and name_part in row.get("Kernel_Name", ""):
+                    vals.append((int(row.get("Dispatch_Id", 0)), float(row["Counter_Value"]),
+                                 int(row.get("Grid_Size", 0))))
+    vals.sort()
+    return vals
+
+
+def write_traffic_record(args):
+    """Write profiles/<name>.json and .md from four rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE of the product, FETCH_SIZE and WRITE_SIZE of
+    the 1 GiB copy calibration) found under args.traffic_record, stamped with
+    the hash of the current kernel sources: the record is written only from
+    a measurement, never edited by hand."""
+    import numpy as np
+    d = args.traffic_record
+    kern = args.traffic_kernel
+    fetch = [v for _, v, _ in _counter_rows(os.path.join(d, "fetch"), "FETCH_SIZE", kern)]
+    write = [v for _, v, _ in _counter_rows(os.path.join(d, "write"), "WRITE_SIZE", kern)]
+    grid = [g for _, _, g in _counter_rows(os.path.join(d, "fetch"), "FETCH_SIZE", kern)]
+    cf = [v for _, v, _ in _counter_rows(os.path.join(d, "cfetch"), "FETCH_SIZE", "copyBuffer")]
+    cw = [v for _, v, _ in _counter_rows(os.path.join(d, "cwrite"), "WRITE_SIZE", "copyBuffer")]
+    if not (fetch and write and cf and cw):
+        raise SystemExit("missing counter rows: fetch %d write %d copy %d/%d" % (len(fetch), len(write), len(cf), len(cw)))
+    cfk, cwk = float(np.median(cf)), float(np.median(cw))
+    fs, ws = 1048576.0 / cfk, 1048576.0 / cwk
+    fk, wk = float(np.mean(fetch)), float(np.mean(write))
+    hbm = 1024.0 * (fk * fs + wk * ws)
+    rec = {"kernel": "%s (variant %d), product launch, grid %d threads" % (kern, args.traffic_variant, grid[0]),
+           "variant": args.traffic_variant, "workload": args.traffic_workload,
+           "kernel_source_sha256": kernel_source_hash(),
+           "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+           "copy_fetch_kib_per_GiB": cfk, "copy_write_kib_per_GiB": cwk,
+           "fetch_scale": fs, "write_scale": ws, "hbm_bytes_per_launch": hbm,
+           "dispatches": {"fetch": fetch, "write": write},
+           "commands": args.traffic_commands.split(";;") if args.traffic_commands else [],
+           "kernel_source_files": [os.path.relpath(x, ROOT) for x in KERNEL_SRC]}
+    base = os.path.join(ROOT, "profiles", args.traffic_name)
+    with open(base + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = ["# HBM traffic of %s, %s" % (kern, args.traffic_workload), "",
+             "Written by `bench.py --traffic-record` from the counter runs below; sha256 of",
+             "the kernel sources `%s`." % rec["kernel_source_sha256"], "", "Commands:", ""]
+    lines += ["    " + c for c in rec["commands"]]
+    lines += ["", "| quantity | value |", "|---|---|",
+              "| FETCH_SIZE per launch (KiB) | %.4e (dispatches: %s) |" % (fk, ", ".join("%.4e" % v for v in fetch)),
+              "| WRITE_SIZE per launch (KiB) | %.4e (dispatches: %s) |" % (wk, ", ".join("%.4e" % v for v in write)),
+              "| FETCH_SIZE of a 1 GiB device copy (KiB) | %.6g -> scale %.4f |" % (cfk, fs),
+              "| WRITE_SIZE of a 1 GiB device copy (KiB) | %.6g -> scale %.4f |" % (cwk, ws),
+              "| HBM bytes per launch (scaled) | %.4e |" % hbm, ""]
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(lines))
+    print(json.dumps({"written": base + ".json", "hbm_bytes_per_launch": hbm}))
+
+
 def copy_calibration(gib=1.0, reps=5):
     """Plain device-to-device copies of a known size (the calibration run of
     the HBM byte counters)."""
@@ -351,7 +414,18 @@ def main():
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (HBM counter calibration)")
+    ap.add_argument("--traffic-record", default=None,
+                    help="folder with fetch/ write/ cfetch/ cwrite/ rocprofv3 counter runs: write the "
+                         "profiles/ traffic record from them and exit (no GPU)")
+    ap.add_argument("--traffic-kernel", default="chain_dma<double, 8>")
+    ap.add_argument("--traffic-variant", type=int, default=2)
+    ap.add_argument("--traffic-name", default="traffic_chain_dma_f64_n40_d4096")
+    ap.add_argument("--traffic-workload", default="two-site H_eff.psi, N=40, D=4096, beta=0.5, seed 3, FP64")
+    ap.add_argument("--traffic-commands", default="", help="';;'-separated commands of the counter runs")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

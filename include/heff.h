@@ -38,6 +38,7 @@
 #ifndef HEFF_H
 #define HEFF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -83,9 +84,29 @@ typedef struct {
   const double* const* iso_right;  /* [N-k0-2] host, entry m-1 builds m    */
 } heff_problem;
 
+/* Device memory provider of a context.  alloc(bytes, user) returns device
+ * memory of at least `bytes` bytes on the context's device, aligned to 256
+ * bytes and usable in stream order on the context's stream, or NULL when it
+ * cannot (the call then fails with HEFF_ENOMEM); free(ptr, user) takes back
+ * what alloc returned.  Every device buffer the library makes on behalf of a
+ * context (operator stores, task tables, Davidson basis, truncation and
+ * batch buffers, scratch) comes from it; each object frees through the
+ * provider it was made with, also after its context is destroyed, so the
+ * callbacks and `user` must stay valid until the last such object is freed.
+ * A caching allocator such as PyTorch's can own all device memory this
+ * way. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} heff_alloc;
+
 /* Context bound to HIP device `device` and stream `stream` (a hipStream_t,
- * NULL = the null stream).  One context per host thread. */
-int heff_create(heff_ctx** ctx, int device, void* stream);
+ * NULL = the null stream).  alloc (copied; may be NULL) is the device
+ * memory provider, NULL = hipMalloc / hipFree.  One context per host
+ * thread.  HEFF_EINVAL for a provider with a null callback, HEFF_EHIP for a
+ * device that does not exist. */
+int heff_create(heff_ctx** ctx, int device, void* stream, const heff_alloc* alloc);
 int heff_destroy(heff_ctx* ctx);
 /* Description of the last error on ctx; valid until the next call on it. */
 const char* heff_last_error(const heff_ctx* ctx);
@@ -95,12 +116,23 @@ const char* heff_last_error(const heff_ctx* ctx);
  * two-site product (Sec. II.C).  All inputs are host memory read during
  * the call.  prec_mask: bit (1 << HEFF_FP32) and/or (1 << HEFF_BF16X3)
  * also prepare the FP32 operand copies that both reduced-precision products
- * read (the split-bf16 product splits FP32 values into hi/lo on the fly).  Validates symmetry
- * of h and V (1e-12), sorted non-empty bond tables consistent with the
- * isometry shapes and orthonormal isometry columns (1e-10).  Synchronizes
- * the context stream.  *out is owned by the caller (heff_blocks_free). */
+ * read (the split-bf16 product splits FP32 values into hi/lo on the fly).
+ * Validates the problem first as heff_validate_problem() does (HEFF_EINVAL,
+ * HEFF_ESECTOR).  Synchronizes the context stream.  *out is owned by the
+ * caller (heff_blocks_free). */
 int heff_build_blocks(heff_ctx* ctx, const heff_problem* prob, uint32_t prec_mask,
                       heff_blocks** out);
+/* The checks heff_build_blocks makes before any device work, on the host
+ * only (no context, no device needed): n_orb in [4, 64], electron numbers,
+ * symmetric h and 8-fold symmetric V (1e-12 of the largest entry), sorted
+ * bond tables with positive dimensions <= 65535, the empty blocks' single
+ * sector (0,0) of dimension 1, no out-sector with more kept than reachable
+ * states, orthonormal isometry columns (|M^T M - I| <= 1e-10 over the whole
+ * Gram matrix of every out-sector block, Eq. DefinitionMPS of Sec. II.A),
+ * and at least one two-site block in the target sector.  Returns HEFF_OK,
+ * HEFF_EINVAL or HEFF_ESECTOR; msg (caller-owned, may be NULL) receives a
+ * NUL-terminated description of at most msg_len - 1 characters. */
+int heff_validate_problem(const heff_problem* prob, char* msg, int32_t msg_len);
 int heff_blocks_free(heff_blocks* b);
 
 /* Two-site layout: number of elements and blocks; blk_desc[6*i..] =
@@ -143,6 +175,9 @@ int heff_task_stats_issued(const heff_blocks* b, int v, double* mfma_flops, int6
  * output blocks of `rank` and leaves the other elements of `out` untouched,
  * each block with the same task order, hence the same bits, as the full
  * product.  rank in [0, nranks); nranks = 1 restores the full product.
+ * While nranks > 1 the calls whose result needs every output element
+ * (heff_energy, heff_energy_backward, heff_dav_create, heff_davidson_step)
+ * return HEFF_ESTATE.
  * shard_flops (may be NULL) receives this rank's algorithmic flops per
  * product.  heff_task_stats_variant() then reports the rank's work-groups;
  * the flop statistics stay those of the full product.  Synchronizes the
@@ -232,7 +267,7 @@ int heff_op_arena(const heff_blocks* b, int prec, void* ptr[4], int64_t n_elem[4
 int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
                         const int32_t* pairs, double* g);
 /* heff_integral_gradient(): the derivatives of E = <psi|H_eff|psi> with
- * respect to the one- and two-electron integrals of Eq. Hamiltonian_QC
+ * respect to the one- and two-electron integrals of Sec. II.A, Eq. Hamiltonian
  * (psi: device, FP64, n_elem of p's two-site layout; isometries of p and
  * psi held fixed), as symmetric tensors on the space of real symmetric
  * integrals: for a symmetric change (dh, dV) of the integrals E changes by

@@ -8,6 +8,7 @@
 #include "heff_internal.h"
 #include "../../include/heff.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -267,6 +268,7 @@ struct heff_dav {
   double* Y = nullptr;        // 2*kMaxBasis
   double* cvec = nullptr;     // kMaxBasis
   double* minus1 = nullptr;   // constant
+  Alloc al;                   // provider of the buffers above
 };
 
 extern "C" int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag);
@@ -282,10 +284,9 @@ extern "C" int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag);
 
 static void dav_release(heff_dav* d) {
   double* ptrs[] = {d->V, d->W, d->d, d->r, d->u, d->t, d->scratch, d->G, d->small, d->y, d->yprev, d->col, d->Y, d->cvec, d->minus1};
-  for (double* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (d->x32) (void)hipFree(d->x32);
-  if (d->y32) (void)hipFree(d->y32);
+  for (double* p : ptrs) dev_free(p, d->al);
+  dev_free(d->x32, d->al);
+  dev_free(d->y32, d->al);
 }
 
 extern "C" int heff_dav_create(heff_ctx* ctx, const heff_blocks* b, int32_t m_max, double tol, const double* psi0,
@@ -296,6 +297,10 @@ extern "C" int heff_dav_create(heff_ctx* ctx, const heff_blocks* b, int32_t m_ma
     return HEFF_EINVAL;
   }
   *out = nullptr;
+  if (blocks_sharded(b)) {
+    ctx->err = "heff_dav_create: the product is restricted to one shard's output blocks";
+    return HEFF_ESTATE;
+  }
   int64_t n = 0;
   heff_psi_layout(b, &n, nullptr, nullptr, nullptr);
   heff_dav* D = new (std::nothrow) heff_dav;
@@ -307,15 +312,14 @@ extern "C" int heff_dav_create(heff_ctx* ctx, const heff_blocks* b, int32_t m_ma
   D->tol = tol;
   D->n = n;
   hipStream_t s = ctx->stream;
-  auto A = [&](double** p, size_t cnt) { return hipMalloc(p, cnt * sizeof(double)); };
+  D->al = ctx->alloc;
+  auto A = [&](double** p, size_t cnt) { return (*p = (double*)dev_alloc(std::max<size_t>(cnt, 1) * sizeof(double), D->al)) != nullptr; };
+  auto F = [&](float** p, size_t cnt) { return (*p = (float*)dev_alloc(std::max<size_t>(cnt, 1) * sizeof(float), D->al)) != nullptr; };
   size_t slots = (size_t)(m_max + 3);
-  if (A(&D->V, slots * n) != hipSuccess || A(&D->W, slots * n) != hipSuccess || A(&D->d, n) != hipSuccess ||
-      A(&D->r, n) != hipSuccess || A(&D->u, n) != hipSuccess || A(&D->t, n) != hipSuccess ||
-      A(&D->scratch, 512 * kMaxBasis) != hipSuccess || A(&D->G, kMaxBasis * kMaxBasis) != hipSuccess ||
-      A(&D->small, 8) != hipSuccess || A(&D->y, kMaxBasis) != hipSuccess || A(&D->yprev, kMaxBasis) != hipSuccess ||
-      A(&D->col, kMaxBasis) != hipSuccess || A(&D->Y, 2 * kMaxBasis) != hipSuccess ||
-      A(&D->cvec, kMaxBasis) != hipSuccess || A(&D->minus1, 1) != hipSuccess ||
-      hipMalloc(&D->x32, n * sizeof(float)) != hipSuccess || hipMalloc(&D->y32, n * sizeof(float)) != hipSuccess) {
+  if (!A(&D->V, slots * n) || !A(&D->W, slots * n) || !A(&D->d, n) || !A(&D->r, n) || !A(&D->u, n) ||
+      !A(&D->t, n) || !A(&D->scratch, 512 * kMaxBasis) || !A(&D->G, kMaxBasis * kMaxBasis) || !A(&D->small, 8) ||
+      !A(&D->y, kMaxBasis) || !A(&D->yprev, kMaxBasis) || !A(&D->col, kMaxBasis) || !A(&D->Y, 2 * kMaxBasis) ||
+      !A(&D->cvec, kMaxBasis) || !A(&D->minus1, 1) || !F(&D->x32, n) || !F(&D->y32, n)) {
     dav_release(D);
     delete D;
     ctx->err = "heff_dav_create: device allocation failed";
@@ -343,6 +347,10 @@ extern "C" int heff_davidson_step(heff_ctx* ctx, heff_dav* D, int prec, double* 
   if (!ctx) return HEFF_EINVAL;
   if (!D) { ctx->err = "null solver"; return HEFF_EINVAL; }
   if (D->converged) { ctx->err = "Davidson already converged"; return HEFF_ESTATE; }
+  if (blocks_sharded(D->blocks)) {
+    ctx->err = "the product is restricted to one shard's output blocks";
+    return HEFF_ESTATE;
+  }
   hipStream_t s = ctx->stream;
   const int64_t n = D->n;
   const int k = D->k;

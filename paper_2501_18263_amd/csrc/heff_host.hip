@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,6 +32,7 @@
 #include <set>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace heff {
@@ -47,10 +49,39 @@ struct Error : std::runtime_error {
       throw Error(HEFF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));              \
   } while (0)
 
-// ------------------------------------------------------------------ device buffer
+// ------------------------------------------------------------------ device memory
+thread_local Alloc tl_alloc;
+
+void* dev_alloc(size_t bytes, const Alloc& a) {
+  void* p = nullptr;
+  if (a.fa) {
+    p = a.fa(bytes, a.user);
+    if (p && (reinterpret_cast<uintptr_t>(p) & 255)) {  // the provider broke its alignment promise
+      a.ff(p, a.user);
+      p = nullptr;
+    }
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+void dev_free(void* p, const Alloc& a) {
+  if (!p) return;
+  if (a.fa) a.ff(p, a.user);
+  else (void)hipFree(p);
+}
+
+// C-ABI calls on a context allocate through its provider
+struct AllocScope {
+  Alloc saved;
+  explicit AllocScope(const heff_ctx* c) : saved(tl_alloc) { tl_alloc = c ? c->alloc : Alloc{}; }
+  ~AllocScope() { tl_alloc = saved; }
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Alloc al;  // provider p came from
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -58,15 +89,13 @@ struct DevBuf {
   void alloc(size_t n) {
     release();
     if (n == 0) n = 256;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw Error(HEFF_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
-    }
+    al = tl_alloc;
+    p = dev_alloc(n, al);
+    if (!p) throw Error(HEFF_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
     bytes = n;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    dev_free(p, al);
     p = nullptr;
     bytes = 0;
   }
@@ -323,24 +352,8 @@ static void make_iso(Iso& iso, const Bond& old, const Bond& nw, const double* ho
       if (qi >= 0) r += old.dim[qi];
     }
     if (r < nw.dim[q]) throw Error(HEFF_EINVAL, std::string(what) + ": more kept states than reachable states");
-    iso.qoff[q] = off;
-    // orthonormality: column norms and a few column pairs
-    const double* M = host + off;
-    int D = nw.dim[q];
-    int npair = std::min(D, 8);
-    for (int a = 0; a < D; ++a) {
-      for (int bb = 0; bb < npair; ++bb) {
-        int b2 = (a + bb * 7919) % D;
-        if (bb > 0 && b2 == a) continue;
-        if (bb == 0) b2 = a;
-        double acc = 0.0;
-        for (int64_t i = 0; i < r; ++i) acc += M[i * D + a] * M[i * D + b2];
-        double want = (a == b2) ? 1.0 : 0.0;
-        if (std::fabs(acc - want) > 1e-10)
-          throw Error(HEFF_EINVAL, std::string(what) + ": isometry columns not orthonormal");
-      }
-    }
-    off += r * D;
+    iso.qoff[q] = off;  // (orthonormality is checked by validate_problem)
+    off += r * (int64_t)nw.dim[q];
   }
   iso.size = off;
   iso.dev.alloc((size_t)std::max<int64_t>(off, 1) * sizeof(double));
@@ -1033,6 +1046,10 @@ struct heff_blocks {
   std::vector<heff::Tile> h_tiles;  // host copies (used to assemble batches)
   std::vector<heff::Task> h_tasks;
   int64_t n_tiles = 0, n_tasks = 0, n_dtasks = 0;
+  // ranks of the output-block shard the product is restricted to (1: the
+  // full product); while > 1 the calls that need every output element
+  // (energies, gradients, Davidson) refuse with HEFF_ESTATE
+  int32_t shard_nranks = 1;
   double flops = 0.0, bytes[3] = {0, 0, 0};
   double vflops[heff::kNumVariants] = {0, 0, 0, 0};  // algorithmic flops per kernel variant
   double vissued[heff::kNumVariants] = {0, 0, 0, 0};  // matrix-instruction flops of the FP64/FP32 kernel
@@ -1418,12 +1435,124 @@ static void validate_ints(const heff_problem* p, Ints& I) {
   }
 }
 
+// Largest |(M^T M - I)_ij| of an r x d row-major matrix (rank-one updates
+// row by row over the upper triangle).
+static double gram_defect(const double* M, int64_t r, int d) {
+  std::vector<double> G((size_t)d * d, 0.0);
+  for (int64_t i = 0; i < r; ++i) {
+    const double* row = M + i * d;
+    for (int a = 0; a < d; ++a) {
+      const double x = row[a];
+      if (x == 0.0) continue;
+      double* g = G.data() + (size_t)a * d;
+      for (int b = a; b < d; ++b) g[b] += x * row[b];
+    }
+  }
+  double worst = 0.0;
+  for (int a = 0; a < d; ++a)
+    for (int b = a; b < d; ++b) worst = std::max(worst, std::fabs(G[(size_t)a * d + b] - (a == b ? 1.0 : 0.0)));
+  return worst;
+}
+
+// Every check heff_build_blocks makes before it touches the device: sizes,
+// symmetric integrals, sorted bond tables with the empty blocks' single
+// sector, isometry shapes (no more kept than reachable states), orthonormal
+// isometry columns (the whole Gram matrix of every out-sector block, 1e-10)
+// and a non-empty target sector.  Host only.
+static void validate_problem(const heff_problem* p, Ints* ints) {
+  if (!p || !p->h || !p->V || !p->left || !p->right || !p->iso_left || !p->iso_right)
+    throw Error(HEFF_EINVAL, "null argument");
+  const int n = p->n_orb;
+  if (n < 4 || n > 64) throw Error(HEFF_EINVAL, "n_orb must be in [4, 64]");
+  if (p->n_up < 0 || p->n_dn < 0 || p->n_up > n || p->n_dn > n) throw Error(HEFF_EINVAL, "bad electron numbers");
+  Ints local;
+  Ints& I = ints ? *ints : local;
+  validate_ints(p, I);
+  const int k0 = n / 2 - 1, mR = n - k0 - 2;
+  std::vector<Bond> lb, rb;
+  for (int l = 0; l <= k0; ++l) lb.push_back(make_bond(p->left[l], "left bond table"));
+  for (int m = 0; m <= mR; ++m) rb.push_back(make_bond(p->right[m], "right bond table"));
+  if (lb[0].n() != 1 || lb[0].nu[0] != 0 || lb[0].nd[0] != 0 || lb[0].dim[0] != 1 ||
+      rb[0].n() != 1 || rb[0].nu[0] != 0 || rb[0].nd[0] != 0 || rb[0].dim[0] != 1)
+    throw Error(HEFF_EINVAL, "empty blocks must have the single sector (0,0) of dimension 1");
+  // isometry blocks: (host pointer, rows, kept columns, description)
+  struct Job { const double* M; int64_t r; int d; int site; bool left; };
+  std::vector<Job> jobs;
+  auto shapes = [&](const Bond& old, const Bond& nw, const double* host, int site, bool left) {
+    if (!host) throw Error(HEFF_EINVAL, left ? "null left isometry" : "null right isometry");
+    int64_t off = 0;
+    for (int q = 0; q < nw.n(); ++q) {
+      int64_t r = 0;
+      for (int st = 0; st < 4; ++st) {
+        int qi = old.find(nw.nu[q] - SQU[st], nw.nd[q] - SQD[st]);
+        if (qi >= 0) r += old.dim[qi];
+      }
+      if (r < nw.dim[q])
+        throw Error(HEFF_EINVAL, std::string(left ? "left" : "right") + " isometry of site " + std::to_string(site) +
+                                     ": more kept states than reachable states");
+      jobs.push_back({host + off, r, nw.dim[q], site, left});
+      off += r * (int64_t)nw.dim[q];
+    }
+  };
+  for (int l = 0; l < k0; ++l) shapes(lb[l], lb[l + 1], p->iso_left[l], l, true);
+  for (int m = 1; m <= mR; ++m) shapes(rb[m - 1], rb[m], p->iso_right[m - 1], n - m, false);
+  // Gram matrices, spread over host threads (largest blocks first)
+  std::vector<size_t> order(jobs.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return (double)jobs[a].r * jobs[a].d * jobs[a].d > (double)jobs[b].r * jobs[b].d * jobs[b].d;
+  });
+  std::vector<double> defect(jobs.size(), 0.0);
+  std::atomic<size_t> next{0};
+  auto worker = [&]() {
+    for (size_t i; (i = next.fetch_add(1)) < order.size();) {
+      const Job& j = jobs[order[i]];
+      defect[order[i]] = gram_defect(j.M, j.r, j.d);
+    }
+  };
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& t : pool) t.join();
+  for (size_t i = 0; i < jobs.size(); ++i)
+    if (!(defect[i] <= 1e-10))
+      throw Error(HEFF_EINVAL, std::string(jobs[i].left ? "left" : "right") + " isometry of site " +
+                                   std::to_string(jobs[i].site) + ": columns not orthonormal (|M^T M - I| = " +
+                                   std::to_string(defect[i]) + ")");
+  // the target sector must meet at least one two-site block
+  const Bond& bl = lb[k0];
+  const Bond& br = rb[mR];
+  bool any = false;
+  for (int qa = 0; qa < bl.n() && !any; ++qa)
+    for (int sk = 0; sk < 4 && !any; ++sk)
+      for (int sk1 = 0; sk1 < 4 && !any; ++sk1)
+        any = br.find(p->n_up - bl.nu[qa] - SQU[sk] - SQU[sk1], p->n_dn - bl.nd[qa] - SQD[sk] - SQD[sk1]) >= 0;
+  if (!any) throw Error(HEFF_ESECTOR, "no two-site block in the target sector");
+}
+
 }  // namespace heff
 
 // ====================================================================== C ABI
 using namespace heff;
 
-#define ABI_BEGIN try {
+extern "C" int heff_validate_problem(const heff_problem* prob, char* msg, int32_t msg_len) {
+  try {
+    validate_problem(prob, nullptr);
+  } catch (const Error& e) {
+    if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "host allocation failed");
+    return HEFF_ENOMEM;
+  }
+  if (msg && msg_len > 0) msg[0] = 0;
+  return HEFF_OK;
+}
+
+#define ABI_BEGIN                    \
+  heff::AllocScope alloc_scope_(ctx); \
+  try {
 #define ABI_END(ctx)                                                \
   }                                                                 \
   catch (const Error& e) {                                          \
@@ -1445,14 +1574,17 @@ namespace heff {
 // (so the variants run concurrently: the small-block variants are bound by
 // their longest work item and fill the chip while the large one runs) and
 // joined back into it.  All default priority.
-static void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
-  if (!c->fork) {
-    HCHECK(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
-    for (int v = 0; v < kNumVariants; ++v) {
-      HCHECK(hipStreamCreateWithFlags(&c->vs[v], hipStreamNonBlocking));
-      HCHECK(hipEventCreateWithFlags(&c->join[v], hipEventDisableTiming));
-    }
+static hipError_t make_variant_streams(heff_ctx* c) {
+  if (c->fork) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  for (int v = 0; v < kNumVariants && e == hipSuccess; ++v) {
+    e = hipStreamCreateWithFlags(&c->vs[v], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[v], hipEventDisableTiming);
   }
+  return e;
+}
+static void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
+  HCHECK(make_variant_streams(c));
   HCHECK(hipEventRecord(c->fork, c->stream));
   for (int v = 0; v < kNumVariants; ++v) {
     HCHECK(hipStreamWaitEvent(c->vs[v], c->fork, 0));
@@ -1467,9 +1599,10 @@ static void join_variants(heff_ctx* c) {
 }
 }  // namespace heff
 
-extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
+extern "C" int heff_create(heff_ctx** out, int device, void* stream, const heff_alloc* alloc) {
   if (!out) return HEFF_EINVAL;
   *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->free)) return HEFF_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return HEFF_EHIP;
   if (hipSetDevice(device) != hipSuccess) return HEFF_EHIP;
@@ -1477,6 +1610,13 @@ extern "C" int heff_create(heff_ctx** out, int device, void* stream) {
   if (!c) return HEFF_ENOMEM;
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(stream);
+  if (alloc) c->alloc = Alloc{alloc->alloc, alloc->free, alloc->user};
+  // the product's variant streams exist from here on (no product call
+  // creates runtime objects)
+  if (make_variant_streams(c) != hipSuccess) {
+    heff_destroy(c);
+    return HEFF_EHIP;
+  }
   *out = c;
   return HEFF_OK;
 }
@@ -1503,13 +1643,12 @@ extern "C" const char* heff_last_error(const heff_ctx* c) { return c ? c->err.c_
 extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t prec_mask, heff_blocks** out) {
   if (!ctx) return HEFF_EINVAL;
   ABI_BEGIN
-  if (!p || !out || !p->h || !p->V || !p->left || !p->right || !p->iso_left || !p->iso_right)
-    throw Error(HEFF_EINVAL, "null argument");
+  if (!out) throw Error(HEFF_EINVAL, "null argument");
   *out = nullptr;
-  const int n = p->n_orb;
-  if (n < 4 || n > 64) throw Error(HEFF_EINVAL, "n_orb must be in [4, 64]");
-  if (p->n_up < 0 || p->n_dn < 0 || p->n_up > n || p->n_dn > n) throw Error(HEFF_EINVAL, "bad electron numbers");
   if (prec_mask & ~((1u << HEFF_FP32) | (1u << HEFF_BF16X3) | 1u)) throw Error(HEFF_EINVAL, "bad prec_mask");
+  Ints I;
+  validate_problem(p, &I);
+  const int n = p->n_orb;
   HCHECK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   auto B = std::make_unique<heff_blocks>();
@@ -1522,8 +1661,6 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
   B->k0 = n / 2 - 1;
   B->prec_mask = prec_mask;
   const int k0 = B->k0, mR = n - k0 - 2, nmode = 2 * n;
-  Ints I;
-  validate_ints(p, I);
   std::vector<Bond> lb, rb;
   for (int l = 0; l <= k0; ++l) lb.push_back(make_bond(p->left[l], "left bond table"));
   for (int m = 0; m <= mR; ++m) rb.push_back(make_bond(p->right[m], "right bond table"));
@@ -1641,9 +1778,12 @@ extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, in
   HCHECK(hipStreamSynchronize(ctx->stream));  // no product still reads the old lists
   b->mwork.upload_lists(lists, ctx->stream);
   HCHECK(hipStreamSynchronize(ctx->stream));
+  b->shard_nranks = nranks;
   if (shard_flops) *shard_flops = load[rank];
   ABI_END(ctx)
 }
+
+bool heff::blocks_sharded(const heff_blocks* b) { return b && b->shard_nranks > 1; }
 
 extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
   if (!ctx) return HEFF_EINVAL;
@@ -2404,6 +2544,7 @@ extern "C" int heff_energy(heff_ctx* ctx, const heff_blocks* b, int prec, const 
   if (!ctx) return HEFF_EINVAL;
   ABI_BEGIN
   if (!b || !psi || !E) throw Error(HEFF_EINVAL, "null argument");
+  if (b->shard_nranks > 1) throw Error(HEFF_ESTATE, "the product is restricted to one shard's output blocks");
   if (prec != HEFF_FP64 && prec != HEFF_FP32) throw Error(HEFF_ENOTSUP, "energy is available in FP64 and FP32");
   HCHECK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
@@ -2431,6 +2572,7 @@ extern "C" int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int pre
   if (!ctx) return HEFF_EINVAL;
   ABI_BEGIN
   if (!b || !psi) throw Error(HEFF_EINVAL, "null argument");
+  if (b->shard_nranks > 1) throw Error(HEFF_ESTATE, "the product is restricted to one shard's output blocks");
   if (prec != HEFF_FP64 && prec != HEFF_FP32) throw Error(HEFF_ENOTSUP, "gradients are available in FP64 and FP32");
   if (dpsi == psi) throw Error(HEFF_EINVAL, "psi and dpsi alias");
   HCHECK(hipSetDevice(ctx->device));

@@ -165,10 +165,34 @@ hipError_t launch_scale_f64(double* x, int64_t n, double a, hipStream_t s);
 hipError_t launch_scale_f32(float* x, int64_t n, float a, hipStream_t s);
 }  // namespace heff
 
+struct heff_blocks;
+namespace heff {
+// whether every later product on b writes only one shard's output blocks
+bool blocks_sharded(const heff_blocks* b);
+}  // namespace heff
+
+namespace heff {
+// Device memory provider (the heff_alloc callbacks of a context, or
+// hipMalloc / hipFree when fa is null).  Every object keeps the provider its
+// memory came from and frees through it.
+struct Alloc {
+  void* (*fa)(size_t, void*) = nullptr;
+  void (*ff)(void*, void*) = nullptr;
+  void* user = nullptr;
+};
+// provider of the context whose C-ABI call runs on this thread (contexts
+// are used by one host thread at a time)
+extern thread_local Alloc tl_alloc;
+// nullptr when the provider refuses (or hipMalloc fails)
+void* dev_alloc(size_t bytes, const Alloc& a);
+void dev_free(void* p, const Alloc& a);
+}  // namespace heff
+
 // context object behind the opaque heff_ctx handle of the C ABI
 struct heff_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  heff::Alloc alloc;  // device memory provider of every object made on it
   std::string err;
   // per-variant kernel timing of the product (HIP events on the variant's stream)
   bool timing = false;

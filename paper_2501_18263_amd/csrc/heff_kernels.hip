@@ -594,7 +594,9 @@ struct Smem {
 // What the matrix work of a step needs (filled when its loads are issued),
 // packed to keep the three records of the ring in few scalar registers:
 // bc = b | c << 16; m = flags (bits 0-8) | ph << 9 | valid << 10 |
-// cnt << 11 (ring loads per wave, < 32) | s << 16 (slice index).
+// cnt << 11 (ring loads per wave, < 64) | s << 17 (slice index).  A step
+// issues at most 2 NT + 8 loads per wave (dword loads of NT op(X) blocks
+// and of the wave's op(L) block), so six bits hold the count.
 struct Rec {
   double f;
   uint32_t bc, m;
@@ -603,8 +605,8 @@ struct Rec {
   __device__ __forceinline__ uint32_t flags() const { return m & 0x1ff; }
   __device__ __forceinline__ int ph() const { return (int)((m >> 9) & 1); }
   __device__ __forceinline__ bool valid() const { return (m >> 10) & 1; }
-  __device__ __forceinline__ int cnt() const { return (int)((m >> 11) & 31); }
-  __device__ __forceinline__ int s() const { return (int)(m >> 16); }
+  __device__ __forceinline__ int cnt() const { return (int)((m >> 11) & 63); }
+  __device__ __forceinline__ int s() const { return (int)(m >> 17); }
 };
 template <typename T, int NT>
 using Ring = Rec[Cfg<T, NT>::stages];
@@ -783,7 +785,8 @@ __device__ __forceinline__ void issue(Rec& rec, Cursor& cu, Task& t, Task& pre, 
                             lc, wave);
     }
   }
-  rec.m = (fl & 0x1ff) | ((uint32_t)cu.ph << 9) | (1u << 10) | ((uint32_t)cnt << 11) | ((uint32_t)cu.s << 16);
+  static_assert(2 * NT + 8 < 64, "ring loads per wave must fit the record's six-bit count");
+  rec.m = (fl & 0x1ff) | ((uint32_t)cu.ph << 9) | (1u << 10) | ((uint32_t)cnt << 11) | ((uint32_t)cu.s << 17);
   ivalid = next_step(cu, t, pre, tasks, t1);
 }
 

@@ -42,11 +42,67 @@ class _Problem(ctypes.Structure):
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
-_lib.heff_create.argtypes = [ctypes.POINTER(_vp), _i, _vp]
+
+# heff_alloc: device memory provider callbacks
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Alloc(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+# user key -> (alloc(nbytes) -> int address or 0, free(address)); keys start
+# at 1 (a zero `user` arrives as None).  Entries live as long as the module:
+# library objects free through them after their context is gone.
+_PROVIDERS = {}
+
+
+def _alloc_cb(nbytes, user):
+    try:
+        return _PROVIDERS[user][0](int(nbytes)) or None
+    except Exception:  # any failure is a refusal: the library reports HEFF_ENOMEM
+        return None
+
+
+def _free_cb(ptr, user):
+    try:
+        _PROVIDERS[user][1](int(ptr))
+    except Exception:
+        pass
+
+
+_ALLOC_CB = _ALLOC_FN(_alloc_cb)
+_FREE_CB = _FREE_FN(_free_cb)
+
+
+def _torch_provider(device, stream):
+    """PyTorch's caching allocator on (device, stream): the library's device
+    memory is then owned by torch."""
+    import torch
+    handle = stream.cuda_stream
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(max(n, 1), device, handle)
+
+    def free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
+def _register_provider(fns):
+    key = len(_PROVIDERS) + 1
+    _PROVIDERS[key] = fns
+    return _Alloc(_ALLOC_CB, _FREE_CB, key)
+
+
+_lib.heff_create.argtypes = [ctypes.POINTER(_vp), _i, _vp, ctypes.POINTER(_Alloc)]
 _lib.heff_destroy.argtypes = [_vp]
 _lib.heff_last_error.argtypes = [_vp]
 _lib.heff_last_error.restype = ctypes.c_char_p
 _lib.heff_build_blocks.argtypes = [_vp, ctypes.POINTER(_Problem), ctypes.c_uint32, ctypes.POINTER(_vp)]
+_lib.heff_validate_problem.argtypes = [ctypes.POINTER(_Problem), ctypes.c_char_p, ctypes.c_int32]
 _lib.heff_blocks_free.argtypes = [_vp]
 _lib.heff_psi_layout.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
@@ -91,7 +147,8 @@ _lib.heff_batch_free.argtypes = [_vp]
 _lib.heff_debug_op.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
 _lib.heff_debug_op.restype = ctypes.c_int64
 
-EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_blocks_free",
+EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_validate_problem",
+            "heff_blocks_free",
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
             "heff_task_stats_variant", "heff_task_stats_issued", "heff_blocks_shard", "heff_energy", "heff_energy_backward",
@@ -113,17 +170,33 @@ def _ptr(t):
 
 
 
-class Context:
-    """Library context on a device, bound to torch's current stream."""
+HEFF_EINVAL, HEFF_ESECTOR, HEFF_ENOMEM, HEFF_EHIP, HEFF_ENOTSUP, HEFF_ENOCONV, HEFF_ESTATE = range(-1, -8, -1)
 
-    def __init__(self, device=0, stream=None):
+
+class Context:
+    """Library context on a device, bound to torch's current stream.
+
+    allocator: "torch" (default: every device buffer of the library comes
+    from PyTorch's caching allocator on this stream), "hip" (the library's
+    own hipMalloc / hipFree) or a pair of callables (alloc(nbytes) -> device
+    address or 0, free(address))."""
+
+    def __init__(self, device=0, stream=None, allocator="torch"):
         import torch
         self.device = device
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        if allocator == "hip":
+            prov = None
+        elif allocator == "torch":
+            prov = _register_provider(_torch_provider(device, stream))
+        else:
+            prov = _register_provider(tuple(allocator))
+        self._prov = prov
         h = _vp()
-        rc = _lib.heff_create(ctypes.byref(h), device, _vp(stream.cuda_stream))
+        rc = _lib.heff_create(ctypes.byref(h), device, _vp(stream.cuda_stream),
+                              ctypes.byref(prov) if prov is not None else None)
         if rc != 0:
             raise HeffError(rc, "heff_create failed")
         self._h = h
@@ -196,6 +269,16 @@ def _marshal(p, keep, h=None, V=None):
     keep += [h, V, il, ir]
     return _Problem(p.n_orb, p.n_up, p.n_dn, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                     V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), left, right, il, ir)
+
+
+def validate_problem(problem, h=None, V=None):
+    """Host-only checks of a problem (heff_validate_problem; no device):
+    returns (code, message), code 0 when the problem is valid."""
+    keep = []
+    prob = _marshal(problem, keep, h, V)
+    buf = ctypes.create_string_buffer(512)
+    rc = _lib.heff_validate_problem(ctypes.byref(prob), buf, len(buf))
+    return rc, buf.value.decode()
 
 
 class _DeviceArray:

@@ -44,6 +44,15 @@ def test_traffic_record_is_consistent():
     assert abs(t["write_scale"] - 1048576.0 / t["copy_write_kib_per_GiB"]) <= 1e-12
     hbm = 1024.0 * (fetch * t["fetch_scale"] + write * t["write_scale"])
     assert abs(hbm - t["hbm_bytes_per_launch"]) <= 1e-9 * hbm
-    # reported only for its own variant and sources
-    assert bench.measured_traffic(t["variant"]) == t["hbm_bytes_per_launch"]
+    # reported only for its own variant and only while the kernel sources
+    # are the ones the counters were taken on (the record is written by
+    # bench.py --traffic-record from a measurement, never re-stamped)
     assert bench.measured_traffic(t["variant"] + 1) is None
+    orig = bench.kernel_source_hash
+    try:
+        bench.kernel_source_hash = lambda: t["kernel_source_sha256"]
+        assert bench.measured_traffic(t["variant"]) == t["hbm_bytes_per_launch"]
+        bench.kernel_source_hash = lambda: "0" * 64
+        assert bench.measured_traffic(t["variant"]) is None
+    finally:
+        bench.kernel_source_hash = orig

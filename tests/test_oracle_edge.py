@@ -1,5 +1,6 @@
 """Oracle pins on the degenerate cases of the two-site product (Sec. II.A,
-the effective Hamiltonian of Eq. (3) restricted to one U(1)xU(1) sector).
+the Hamiltonian of Eq. Hamiltonian projected on the two-site space and
+restricted to one U(1)xU(1) sector).
 
 Each case has a closed form independent of the block algebra:
   * no electrons: every term of H holds an annihilator, so H_eff = 0;

@@ -1,5 +1,6 @@
 """Planted mistakes in the oracle, on the CPU: each plausible slip in the
-block algebra of the two-site product (Sec. II.A, Eq. (3)) must make one of
+block algebra of the two-site product (Sec. II.A, Eq. Hamiltonian, and
+Sec. II.C) must make one of
 the pins fail.  The pins used are the explicit projection P^T H P (O-DEF,
 built from the determinant Hamiltonian, no code shared with the block
 oracle) and the closed-shell energy of a completely filled problem.  A
