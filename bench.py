@@ -149,27 +149,104 @@ def copy_calibration(gib=1.0, reps=5):
                       "GB_per_s": 8 * n / dt / 1e9}), flush=True)
 
 
-def cpu_baseline(n_orb=16, d_max=256, seed=5):
-    """The block-sparse CPU oracle on a bounded sample (N=16, D=256: the
-    same Hamiltonian family, every term, one product); rate in TFLOP/s from
-    the oracle's own flop count."""
-    import numpy as np  # noqa: F401
+CB_CONFIG = (24, 1024, 2)  # N, D, seed of the CPU baseline sample (the N=24, D=1024 configuration)
+
+
+def _apply_chunk(i):
+    """One worker's share of the oracle product: every W-th term, starting
+    at term i (the terms and psi come from the forked parent)."""
+    from oracle import block
+    g = _CB_STATE
+    t0 = time.perf_counter()
+    block.FLOPS[0] = 0.0
+    y = block.apply(g["p"], g["terms"][i::g["w"]], g["psi"])
+    return y, time.perf_counter() - t0, block.FLOPS[0]
+
+
+_CB_STATE = {}
+
+
+def cpu_baseline_worker(args):
+    """CPU-only process of the baseline (never touches the GPU): build the
+    oracle's operators and term list for the sample, report readiness, wait
+    for the parent's go (so the timed product does not share the host with
+    the GPU measurements), then time one oracle product spread over a pool
+    of single-threaded worker processes (terms dealt round-robin, partial
+    outputs summed)."""
+    import multiprocessing as mp
+
+    import numpy as np
 
     from oracle import block
     from paper_2501_18263_amd import synth
 
-    p = synth.make_problem(n_orb, d_max, seed)
+    n, d, seed = CB_CONFIG
+    t0 = time.perf_counter()
+    p = synth.make_problem(n, d, seed)
     terms = block.heff_terms(p)
     psi = synth.random_psi(p)
-    block.FLOPS[0] = 0.0
+    t_build = time.perf_counter() - t0
+    w = args.cb_workers
+    _CB_STATE.update(p=p, terms=terms, psi=psi, w=w)
+    pool = mp.get_context("fork").Pool(w)
+    pool.map(abs, range(w))  # workers up before the timed product
+    print("ready", flush=True)
+    sys.stdin.readline()
     t0 = time.perf_counter()
-    block.apply(p, terms, psi)
+    parts = pool.map(_apply_chunk, range(w))
+    y = np.sum([q[0] for q in parts], axis=0)
     dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": block.FLOPS[0] / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": "O-BLOCK product, N=%d D=%d (%d-dim psi, %d terms), %.1f s" % (
-                n_orb, d_max, synth.psi_size(p), len(terms), dt)}
+    pool.close()
+    pool.join()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]
+        blas = "%s %s" % (blas.get("name", "?"), blas.get("version", ""))
+    except Exception:
+        blas = "unknown"
+    print(json.dumps({"seconds": dt, "workers": w, "build_s": t_build, "psi_dim": int(psi.size),
+                      "terms": len(terms), "oracle_flops": float(sum(q[2] for q in parts)),
+                      "worker_seconds": [q[1] for q in parts], "checksum": float(y @ psi),
+                      "cpu_model": model, "blas": blas,
+                      "host_cpus": len(os.sched_getaffinity(0))}), flush=True)
+
+
+def cpu_baseline_start():
+    """Start the baseline's CPU process before anything touches the GPU;
+    its build overlaps the GPU measurements."""
+    import subprocess
+    w = max(1, min(16, len(os.sched_getaffinity(0))))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                             "--cb-workers", str(w)], stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                            text=True, env=env)
+
+
+def cpu_baseline_finish(proc, flops_alg):
+    """Let the baseline process time its product (after the GPU work) and
+    turn it into the oracle's rate in algorithmic flops of the sample."""
+    line = proc.stdout.readline().strip()
+    if line != "ready":
+        proc.kill()
+        raise RuntimeError("CPU baseline process failed: %r" % line)
+    proc.stdin.write("go\n")
+    proc.stdin.flush()
+    r = json.loads(proc.stdout.readline())
+    proc.wait(timeout=60)
+    n, d, seed = CB_CONFIG
+    single = flops_alg / sum(r["worker_seconds"])
+    return {"value": flops_alg / r["seconds"] / 1e12, "unit": "TFLOP/s", "cores": r["workers"], "kind": "oracle",
+            "sample": "one O-BLOCK product (FP64 NumPy) at N=%d D=%d seed %d (%d-dim psi, %d terms), terms dealt "
+                      "over %d single-threaded worker processes, %.1f s; rate = the library's algorithmic flops "
+                      "of that product (%.3e) / wall time" % (n, d, seed, r["psi_dim"], r["terms"], r["workers"],
+                                                              r["seconds"], flops_alg),
+            "single_thread_tflops": single / 1e12, "cpu_model": r["cpu_model"], "blas": r["blas"],
+            "host_cpus": r["host_cpus"], "oracle_build_s": r["build_s"], "oracle_executed_flops": r["oracle_flops"]}
 
 
 def autotune_batch(bt, trials=3):
@@ -414,6 +491,8 @@ def main():
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB (HBM counter calibration)")
+    ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cb-workers", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--traffic-record", default=None,
                     help="folder with fetch/ write/ cfetch/ cwrite/ rocprofv3 counter runs: write the "
                          "profiles/ traffic record from them and exit (no GPU)")
@@ -423,6 +502,9 @@ def main():
     ap.add_argument("--traffic-workload", default="two-site H_eff.psi, N=40, D=4096, beta=0.5, seed 3, FP64")
     ap.add_argument("--traffic-commands", default="", help="';;'-separated commands of the counter runs")
     args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args)
+        return
     if args.traffic_record:
         write_traffic_record(args)
         return
@@ -449,6 +531,8 @@ def main():
     if args.workload == "shards":
         bench_shards(args)
         return
+
+    cb_proc = None if args.no_cpu_baseline else cpu_baseline_start()  # before the GPU is touched
 
     import numpy as np  # noqa: F401
     import torch
@@ -571,8 +655,13 @@ def main():
         "roofline": roof,
         "by_precision": res,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+    if cb_proc is not None:
+        n, d, seed = CB_CONFIG
+        Bc = heff.Blocks(ctx, synth.make_problem(n, d, seed))
+        f_c = Bc.stats()["flops"]
+        Bc.close()
+        out["cpu_baseline"] = cpu_baseline_finish(cb_proc, f_c)
+        log("cpu baseline: %s" % out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 
 

@@ -285,10 +285,12 @@ int heff_integral_gradient(heff_ctx* ctx, const heff_problem* p, const double* p
  * products (heff_apply, heff_energy and the Davidson steps): 0 automatic
  * (the default: the LDS-ring kernel when the product has blocks wider than
  * 64, else the register-staged kernel), 1 the register-staged kernel for
- * every width, 2 the ring kernel for every width.  The families compute
- * the same sums in the same order (bitwise
- * identical results); the choice only moves time.  Errors: HEFF_EINVAL
- * (null context, mode outside 0..2). */
+ * every width, 2 the ring kernel for every width, 3 the ring kernel for
+ * every width with its 16-byte loads switched off (every operand slice
+ * moves by dword loads, the path the ring kernel otherwise takes only where
+ * a 16-byte load could pass the end of a buffer).  The families compute
+ * the same sums in the same order (bitwise identical results); the choice
+ * only moves time.  Errors: HEFF_EINVAL (null context, mode outside 0..3). */
 int heff_set_fp64_kernel(heff_ctx* ctx, int32_t mode);
 
 /* Davidson eigensolver for the lowest eigenpair of H_eff (the Diag_H step).

@@ -1817,7 +1817,12 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     set_limits(bs, b->L->store.dev, b->Ltmp.tmp.dev, b->n_elem, b->R->store.dev, b->Rtmp.tmp.dev);
     hipStream_t vs[kNumVariants];
     fork_variants(ctx, vs);
-    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, vs, ev, ctx->fp64_kernel));
+    int mode = ctx->fp64_kernel;
+    if (mode == kFp64RingDword) {  // no buffer lengths known: the ring kernel moves single dwords
+      for (int i = 0; i < 6; ++i) bs.lim[i] = 0;
+      mode = kFp64Ring;
+    }
+    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, vs, ev, mode));
     join_variants(ctx);
   } else if (prec == HEFF_FP32) {
     if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
@@ -2603,13 +2608,9 @@ extern "C" int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int pre
   ABI_END(ctx)
 }
 
-// dE/dh and dE/dV of E = <psi|H_eff(h, V)|psi> (isometries and psi fixed),
-// as symmetric tensors.  E is linear in the integrals, so each component is
-// an energy: E with the indicator of one symmetry orbit of indices as the
-// integrals equals the orbit size times the common component.
 extern "C" int heff_set_fp64_kernel(heff_ctx* ctx, int32_t mode) {
   if (!ctx) return HEFF_EINVAL;
-  if (mode < kFp64Auto || mode > kFp64Ring) {
+  if (mode < kFp64Auto || mode > kFp64RingDword) {
     ctx->err = "unknown FP64 kernel family";
     return HEFF_EINVAL;
   }
@@ -2617,6 +2618,10 @@ extern "C" int heff_set_fp64_kernel(heff_ctx* ctx, int32_t mode) {
   return HEFF_OK;
 }
 
+// dE/dh and dE/dV of E = <psi|H_eff(h, V)|psi> (isometries and psi fixed),
+// as symmetric tensors.  E is linear in the integrals, so each component is
+// an energy: E with the indicator of one symmetry orbit of indices as the
+// integrals equals the orbit size times the common component.
 extern "C" int heff_integral_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, double* gh,
                                       double* gV) {
   if (!ctx) return HEFF_EINVAL;

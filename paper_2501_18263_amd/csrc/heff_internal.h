@@ -104,7 +104,9 @@ struct WorkSet {
 // the narrower ones; register staging otherwise), kFp64Staged (register
 // staging everywhere) or kFp64Ring (the ring for every width).  The
 // families give bitwise identical results.
-enum { kFp64Auto = 0, kFp64Staged = 1, kFp64Ring = 2 };
+// kFp64RingDword runs the ring kernel with its 16-byte loads switched off
+// (every slice moves by dword loads; the same sums in the same order).
+enum { kFp64Auto = 0, kFp64Staged = 1, kFp64Ring = 2, kFp64RingDword = 3 };
 hipError_t launch_mfma_f64(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<double> b,
                            const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr, int mode = kFp64Auto);
 hipError_t launch_mfma_f32(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,

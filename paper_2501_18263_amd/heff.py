@@ -156,7 +156,7 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
-FP64_AUTO, FP64_STAGED, FP64_RING = 0, 1, 2
+FP64_AUTO, FP64_STAGED, FP64_RING, FP64_RING_DWORD = 0, 1, 2, 3
 
 
 class HeffError(RuntimeError):

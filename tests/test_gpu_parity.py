@@ -484,7 +484,10 @@ def test_fp64_kernel_families_agree_bitwise(heff, ctx):
     x = torch.tensor(synth.random_psi(p), device="cuda")
     ys = []
     try:
-        for mode in (heff.FP64_AUTO, heff.FP64_STAGED, heff.FP64_RING):
+        # FP64_RING_DWORD: the ring's dword loads everywhere, the path it
+        # takes where a 16-byte load could pass a buffer's end (a 256-wide
+        # step issues up to 2*16 + 8 of them per wave)
+        for mode in (heff.FP64_AUTO, heff.FP64_STAGED, heff.FP64_RING, heff.FP64_RING_DWORD):
             ctx.set_fp64_kernel(mode)
             y = torch.empty_like(x)
             B.apply(x, y)
@@ -492,7 +495,8 @@ def test_fp64_kernel_families_agree_bitwise(heff, ctx):
     finally:
         ctx.set_fp64_kernel(heff.FP64_AUTO)
     B.close()
-    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
+    for i in (1, 2, 3):
+        assert np.array_equal(ys[0], ys[i]), i
     assert np.abs(ys[0]).max() > 0
     with pytest.raises(heff.HeffError):
-        ctx.set_fp64_kernel(3)
+        ctx.set_fp64_kernel(4)
