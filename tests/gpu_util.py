@@ -4,6 +4,14 @@ import numpy as np
 
 from paper_2501_18263_amd import synth
 
+# Relative bars on the Ritz values of Davidson steps 0, 1, 2 when the
+# library's Davidson is compared with the oracle's on N=8, D=64, seed 1 from
+# the same start vector: ten times the largest deviation that rounding-level
+# perturbations (2e-16 relative) of the product, the diagonal and the
+# Rayleigh quotient cause in the oracle's own Davidson at those steps
+# (pinned on the CPU by test_davidson_transient_is_rounding_sensitive).
+DAVIDSON_STEP_BARS = (1e-14, 1e-12, 1e-9)
+
 
 def flat_oracle_op(op, tab):
     """Concatenate an oracle operator's blocks ordered by in-sector (table order)."""
