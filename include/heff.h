@@ -264,6 +264,22 @@ int heff_energy(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, 
 int heff_energy_backward(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double gE, void* dpsi,
                          void* dL, void* dR);
 int heff_op_arena(const heff_blocks* b, int prec, void* ptr[4], int64_t n_elem[4]);
+
+/* heff_energy_noalloc(): heff_energy() for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, result and errors as
+ * heff_energy(), computed by the same kernels, but it allocates nothing: its
+ * scratch (H psi and the partial sums of the dot product) is one static
+ * device array of 48 MiB + 4 KiB per device, held by every device the
+ * library runs on until the process ends, so psi may have at most 6291456
+ * elements in FP64 and 12582912 in FP32 (HEFF_EINVAL beyond, with a message
+ * that names the limit).  The caller passes psi and E only.  All calls on
+ * one device share that array and every call overwrites it completely:
+ * calls that overlap on one device (several host threads, or contexts on
+ * different streams without ordering between them) race and must not be
+ * issued.  Product timing (heff_timing) is not recorded by this call.
+ * Synchronizes the stream. */
+int heff_energy_noalloc(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, double* E);
 int heff_kappa_gradient(heff_ctx* ctx, const heff_problem* p, const double* psi, int32_t n_pairs,
                         const int32_t* pairs, double* g);
 /* heff_integral_gradient(): the derivatives of E = <psi|H_eff|psi> with

@@ -1612,8 +1612,9 @@ extern "C" int heff_create(heff_ctx** out, int device, void* stream, const heff_
   c->stream = reinterpret_cast<hipStream_t>(stream);
   if (alloc) c->alloc = Alloc{alloc->alloc, alloc->free, alloc->user};
   // the product's variant streams exist from here on (no product call
-  // creates runtime objects)
-  if (make_variant_streams(c) != hipSuccess) {
+  // creates runtime objects); the allocation-free energy's scratch address
+  // on this device is recorded
+  if (make_variant_streams(c) != hipSuccess || noalloc_setup(device) != hipSuccess) {
     heff_destroy(c);
     return HEFF_EHIP;
   }
@@ -1784,6 +1785,7 @@ extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, in
 }
 
 bool heff::blocks_sharded(const heff_blocks* b) { return b && b->shard_nranks > 1; }
+int64_t heff::blocks_n_elem(const heff_blocks* b) { return b ? b->n_elem : 0; }
 
 extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
   if (!ctx) return HEFF_EINVAL;

@@ -171,6 +171,11 @@ struct heff_blocks;
 namespace heff {
 // whether every later product on b writes only one shard's output blocks
 bool blocks_sharded(const heff_blocks* b);
+// elements of b's two-site vector
+int64_t blocks_n_elem(const heff_blocks* b);
+// records the device address of the allocation-free energy's static
+// scratch array on `device` (current); called once per context creation
+hipError_t noalloc_setup(int device);
 }  // namespace heff
 
 namespace heff {

@@ -132,6 +132,7 @@ _lib.heff_batch_layout.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.P
 _lib.heff_batch_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
 _lib.heff_batch_set_grid.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32)]
 _lib.heff_energy.argtypes = [_vp, _vp, _i, _vp, ctypes.POINTER(ctypes.c_double)]
+_lib.heff_energy_noalloc.argtypes = [_vp, _vp, _i, _vp, ctypes.POINTER(ctypes.c_double)]
 _lib.heff_energy_backward.argtypes = [_vp, _vp, _i, _vp, ctypes.c_double, _vp, _vp, _vp]
 _lib.heff_op_arena.argtypes = [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_kappa_gradient.argtypes = [_vp, ctypes.POINTER(_Problem), _vp, ctypes.c_int32,
@@ -152,7 +153,7 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_psi_layout", "heff_task_stats", "heff_apply", "heff_diag", "heff_dav_create",
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
             "heff_task_stats_variant", "heff_task_stats_issued", "heff_blocks_shard", "heff_energy", "heff_energy_backward",
-            "heff_op_arena", "heff_kappa_gradient", "heff_integral_gradient", "heff_set_fp64_kernel", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_op_arena", "heff_energy_noalloc", "heff_kappa_gradient", "heff_integral_gradient", "heff_set_fp64_kernel", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
@@ -354,6 +355,15 @@ class Blocks:
         self._check_vec(psi, prec)
         e = ctypes.c_double()
         self.ctx.check(_lib.heff_energy(self.ctx._h, self._h, prec, _ptr(psi), ctypes.byref(e)))
+        return e.value
+
+    def energy_noalloc(self, psi, prec=FP64):
+        """<psi|H_eff|psi> through heff_energy_noalloc: the same result as
+        energy() without any device allocation (static scratch; psi of at
+        most 6291456 FP64 / 12582912 FP32 elements)."""
+        self._check_vec(psi, prec)
+        e = ctypes.c_double()
+        self.ctx.check(_lib.heff_energy_noalloc(self.ctx._h, self._h, prec, _ptr(psi), ctypes.byref(e)))
         return e.value
 
     def op_arena(self, prec=FP64):
