@@ -119,7 +119,8 @@ const char* heff_last_error(const heff_ctx* ctx);
  * read (the split-bf16 product splits FP32 values into hi/lo on the fly).
  * Validates the problem first as heff_validate_problem() does (HEFF_EINVAL,
  * HEFF_ESECTOR).  Synchronizes the context stream.  *out is owned by the
- * caller (heff_blocks_free). */
+ * caller (heff_blocks_free).  The bit HEFF_KEEP_ENV (below, with the sweep
+ * step) also keeps the environment of later sweep steps. */
 int heff_build_blocks(heff_ctx* ctx, const heff_problem* prob, uint32_t prec_mask,
                       heff_blocks** out);
 /* The checks heff_build_blocks makes before any device work, on the host
@@ -213,6 +214,76 @@ int heff_trunc_info(const heff_trunc* t, int32_t* n_kept, double* discarded, int
 int heff_trunc_get(heff_ctx* ctx, const heff_trunc* t, double* sing, int32_t* nup, int32_t* ndn, int32_t* dim,
                    double* iso_dev);
 int heff_trunc_free(heff_trunc* t);
+
+/* Sweep step (Sec. II.A: the MPS is optimized bond by bond in sweeps;
+ * Sec. IV.A: the SVD, Ren_l and StVec phases around Diag_H).
+ *
+ * HEFF_KEEP_ENV in the prec_mask of heff_build_blocks() keeps what later
+ * sweep steps need: the integrals and the right blocks of every length with
+ * their isometries (device memory of the right blocks of all lengths).
+ *
+ * heff_sweep_right(): from blocks b of the pair (k, k+1) built (or swept to)
+ * with HEFF_KEEP_ENV and the optimized two-site vector psi (device, n_elem
+ * doubles of b's layout): truncates psi to d_keep states exactly as
+ * heff_truncate() does, grows the left block by site k with the truncated
+ * isometry (Ren_l), takes the kept right block of one site fewer, and builds
+ * the blocks of the pair (k+1, k+2) into *out (terms, task table, operand
+ * copies for prec_mask; HEFF_KEEP_ENV is implied: the environment is
+ * shared).  The start vector of the new pair (StVec) is the old state
+ * expressed in the new two-site basis,
+ *   psi'[a', s_k+1, s_k+2, g] = sum A[(s_k, a), a'] psi[a, s_k, s_k+1, b] B[(s_k+2, g), b]
+ * (A the truncated isometry, B the right isometry of site k+2); it is held
+ * by *out (heff_start_vector).  *trunc_out (may be NULL) receives the
+ * truncation result (heff_trunc_info / heff_trunc_get / heff_trunc_free).
+ * Errors: HEFF_ESTATE (no kept environment, sharded blocks, or the pair at
+ * the right end), HEFF_EINVAL (bad arguments, a kept sector wider than the
+ * kernels' 256).  Synchronizes the stream.  *out is freed with
+ * heff_blocks_free(); b stays valid.
+ *
+ * heff_start_vector(): device pointer to the start vector of blocks made by
+ * heff_sweep_right() (n_elem doubles of their layout; owned by the blocks);
+ * HEFF_ESTATE for blocks built otherwise. */
+#define HEFF_KEEP_ENV (1u << 8)
+int heff_sweep_right(heff_ctx* ctx, const heff_blocks* b, const double* psi, int32_t d_keep, uint32_t prec_mask,
+                     heff_blocks** out, heff_trunc** trunc_out);
+int heff_start_vector(const heff_blocks* b, const double** psi);
+
+/* Mode optimization micro-iteration at the pair (Sec. II.B, Fig. microiter):
+ * the two orbitals k, k+1 of the pair are rotated by
+ * U = exp(theta (E_k,k+1 - E_k+1,k)) (U_kk = U_k+1,k+1 = cos theta,
+ * U_k,k+1 = sin theta, U_k+1,k = -sin theta, the identity elsewhere; the same
+ * rotation for both spins), new orbitals c'+_i = sum_a U_ai c+_a.
+ *
+ * heff_rotate_pair(): out = the two-site vector of the same state in the
+ * rotated orbitals: exp(-theta K) on the middle index, K = sum_s
+ * (c+_ks c_k+1,s - c+_k+1,s c_ks) (psi, out: device, n_elem doubles, no
+ * alias).  Synchronizes the stream.
+ *
+ * heff_pair_entropy(): the half-Renyi entropy S_1/2 = 2 ln Tr sqrt(rho) and
+ * the von Neumann entropy S_1 = -Tr rho ln rho of the left part (sites
+ * 0..k) of the normalized state psi, from all singular values over the cut
+ * (the truncation's SVD); either output may be NULL.
+ *
+ * heff_optimize_pair(): the angle minimizing S_1/2 of the rotated state
+ * (S_1/2 has period pi: 16 angles of [-pi/2, pi/2), then golden-section
+ * refinement of the best bracket to 1e-8; one SVD per trial); *theta the
+ * angle, out the rotated vector at it, s_before / s_after (may be NULL)
+ * S_1/2 at 0 and at theta, n_evals (may be NULL) the trials.
+ *
+ * heff_rotate_integrals() (host only, no device): h_out = U^T h U and
+ * V_out_ijkl = sum U_ai U_bj U_ck U_dl V_abcd for the rotation of the
+ * orbital pair (x, y) by theta (h, V as in heff_problem; outputs
+ * caller-owned, may not alias the inputs).  Building blocks from the rotated
+ * integrals with the same isometries gives an H_eff under which the rotated
+ * vector has the energy the old vector had under the old one.
+ * Errors: HEFF_EINVAL (null or aliasing arguments, bad indices, non-finite
+ * theta). */
+int heff_rotate_pair(heff_ctx* ctx, const heff_blocks* b, double theta, const double* psi, double* out);
+int heff_pair_entropy(heff_ctx* ctx, const heff_blocks* b, const double* psi, double* s_half, double* s_vn);
+int heff_optimize_pair(heff_ctx* ctx, const heff_blocks* b, const double* psi, double* out, double* theta,
+                       double* s_before, double* s_after, int32_t* n_evals);
+int heff_rotate_integrals(int32_t n, const double* h, const double* V, int32_t x, int32_t y, double theta,
+                          double* h_out, double* V_out);
 
 /* Batches: n independent problems (each built with FP32 operands) in one
  * persistent launch per kernel variant, captured once into a HIP graph on

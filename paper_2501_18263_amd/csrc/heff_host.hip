@@ -1021,6 +1021,19 @@ struct Term {
   Ref r;    // right-block operator (where 0: R store, 1: R temps)
 };
 
+// What the sweep steps after a build need (kept when the build is asked to
+// keep its environment): the integrals, and the right blocks of every
+// length with the isometries that grew them (the right part shrinks by one
+// site per step of a left-to-right sweep).  Shared by every heff_blocks
+// object of one sweep.
+struct Env {
+  Ints I;
+  int nmode = 0;
+  std::vector<Bond> rb;                       // rb[m]: bond table of the right block of m sites
+  std::vector<std::shared_ptr<Block>> right;  // right[m]
+  std::vector<std::shared_ptr<Iso>> riso;     // riso[m]: isometry of site N-m (m >= 1), old = &rb[m-1]
+};
+
 }  // namespace heff
 
 // ====================================================================== public objects
@@ -1031,7 +1044,9 @@ struct heff_blocks {
   hipStream_t stream = nullptr;
   int n_orb = 0, n_up = 0, n_dn = 0, k0 = 0;
   uint32_t prec_mask = 0;
-  std::unique_ptr<heff::Block> L, R;
+  std::shared_ptr<heff::Block> L, R;
+  std::shared_ptr<heff::Env> env;  // kept for sweeps (HEFF_KEEP_ENV), else null
+  heff::DevBuf start;              // start vector made by the sweep step that built these blocks
   heff::LinPlan Ltmp, Rtmp;
   std::vector<heff::Term> terms;
   // two-site layout
@@ -1646,7 +1661,8 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
   ABI_BEGIN
   if (!out) throw Error(HEFF_EINVAL, "null argument");
   *out = nullptr;
-  if (prec_mask & ~((1u << HEFF_FP32) | (1u << HEFF_BF16X3) | 1u)) throw Error(HEFF_EINVAL, "bad prec_mask");
+  if (prec_mask & ~((1u << HEFF_FP32) | (1u << HEFF_BF16X3) | 1u | HEFF_KEEP_ENV))
+    throw Error(HEFF_EINVAL, "bad prec_mask");
   Ints I;
   validate_problem(p, &I);
   const int n = p->n_orb;
@@ -1678,16 +1694,33 @@ extern "C" int heff_build_blocks(heff_ctx* ctx, const heff_problem* p, uint32_t 
     auto Ln = grow_left(*L, lb[l + 1], iso, l, nmode, I, s);
     L = std::move(Ln);
   }
-  auto R = initial_block(false, nmode, s);
+  // right block; with HEFF_KEEP_ENV every length and its isometry stay
+  std::shared_ptr<Env> env;
+  if (prec_mask & HEFF_KEEP_ENV) {
+    env = std::make_shared<Env>();
+    env->I = I;
+    env->nmode = nmode;
+    env->rb = rb;
+    env->right.resize(mR + 1);
+    env->riso.resize(mR + 1);
+  }
+  const std::vector<Bond>& rbv = env ? env->rb : rb;
+  std::shared_ptr<Block> R = initial_block(false, nmode, s);
+  if (env) env->right[0] = R;
   for (int m = 1; m <= mR; ++m) {
     if (!p->iso_right[m - 1]) throw Error(HEFF_EINVAL, "null right isometry");
-    Iso iso;
-    make_iso(iso, rb[m - 1], rb[m], p->iso_right[m - 1], s, "right isometry");
-    auto Rn = grow_right(*R, rb[m], iso, n - m, nmode, I, s);
-    R = std::move(Rn);
+    auto iso = std::make_shared<Iso>();
+    make_iso(*iso, rbv[m - 1], rbv[m], p->iso_right[m - 1], s, "right isometry");
+    std::shared_ptr<Block> Rn = grow_right(*R, rbv[m], *iso, n - m, nmode, I, s);
+    R = Rn;
+    if (env) {
+      env->right[m] = R;
+      env->riso[m] = iso;
+    }
   }
+  B->env = env;
   B->L = std::move(L);
-  B->R = std::move(R);
+  B->R = R;
   build_psi_layout(*B);
   build_terms(*B, I);
   B->Ltmp.run(s);
@@ -2317,6 +2350,399 @@ extern "C" int heff_trunc_get(heff_ctx* ctx, const heff_trunc* t, double* sing, 
 
 extern "C" int heff_trunc_free(heff_trunc* t) {
   delete t;
+  return HEFF_OK;
+}
+
+// ---------------------------------------------------------------- sweep step (Ren_l, StVec)
+// One step of a left-to-right sweep (Sec. II.A: the MPS is optimized bond by
+// bond; Sec. IV.A names the phases SVD, Ren_l and StVec around Diag_H).  The
+// optimized two-site vector of the pair (k, k+1) is truncated; the left
+// block grows by site k with the truncated isometry A (the same blocking and
+// projection as the build's own left steps); the right part loses site k+2
+// (its block of one site fewer was kept by the build); the pair (k+1, k+2)
+// gets its terms and task table; and the start vector of the new pair is the
+// old state expressed in the new two-site basis,
+//   psi'[a', s1, s2, g] = sum_{s, a, b} A[(s, a), a'] psi[a, s, s1, b] B[(s2, g), b],
+// with B the right isometry of site k+2.  The basis change keeps the mode
+// order (block modes, then the sites in order), so no fermionic sign enters.
+// Every term is one chained block product on the same kernels as H_eff psi.
+static void make_iso_from_device(Iso& iso, const Bond& old, const Bond& nw, const double* dev, int64_t len,
+                                 hipStream_t s) {
+  iso.old = &old;
+  iso.nw = &nw;
+  iso.qoff.resize(nw.n());
+  iso.rowoff.resize(nw.n());
+  int64_t off = 0;
+  for (int q = 0; q < nw.n(); ++q) {
+    int64_t r = 0;
+    for (int st = 0; st < 4; ++st) {
+      iso.rowoff[q][st] = r;
+      int qi = old.find(nw.nu[q] - SQU[st], nw.nd[q] - SQD[st]);
+      if (qi >= 0) r += old.dim[qi];
+    }
+    iso.qoff[q] = off;
+    off += r * (int64_t)nw.dim[q];
+  }
+  if (off != len) throw Error(HEFF_EINVAL, "internal: truncated isometry length does not match its bond");
+  iso.size = off;
+  iso.dev.alloc((size_t)std::max<int64_t>(off, 1) * sizeof(double));
+  if (off) HCHECK(hipMemcpyAsync(iso.dev.p, dev, (size_t)off * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+extern "C" int heff_sweep_right(heff_ctx* ctx, const heff_blocks* b, const double* psi, int32_t d_keep,
+                                uint32_t prec_mask, heff_blocks** out, heff_trunc** trunc_out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out || d_keep <= 0) throw Error(HEFF_EINVAL, "bad argument");
+  *out = nullptr;
+  if (trunc_out) *trunc_out = nullptr;
+  if (prec_mask & ~((1u << HEFF_FP32) | (1u << HEFF_BF16X3) | 1u | HEFF_KEEP_ENV))
+    throw Error(HEFF_EINVAL, "bad prec_mask");
+  if (!b->env) throw Error(HEFF_ESTATE, "the blocks were built without HEFF_KEEP_ENV");
+  if (b->shard_nranks > 1) throw Error(HEFF_ESTATE, "the product is restricted to one shard's output blocks");
+  const int n = b->n_orb, k0 = b->k0, mR = n - k0 - 2;
+  if (mR < 1) throw Error(HEFF_ESTATE, "the pair is already at the right end");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  std::shared_ptr<Env> env = b->env;
+  // SVD step: truncated isometry of site k
+  heff_trunc* tr_raw = nullptr;
+  if (int rc = heff_truncate(ctx, b, psi, d_keep, &tr_raw)) throw Error(rc, ctx->err);
+  std::unique_ptr<heff_trunc> tr(tr_raw);
+  Bond nb;
+  for (size_t i = 0; i < tr->dim.size(); ++i) {
+    nb.nu.push_back(tr->nup[i]);
+    nb.nd.push_back(tr->ndn[i]);
+    nb.dim.push_back(tr->dim[i]);
+    nb.index[{tr->nup[i], tr->ndn[i]}] = (int)i;
+  }
+  if (nb.n() == 0) throw Error(HEFF_ESECTOR, "truncation kept no state");
+  // Ren_l: the left block of k+1 sites
+  Block& Lold = *b->L;
+  Iso isoA;
+  make_iso_from_device(isoA, Lold.bond, nb, tr->iso.as<double>(), tr->iso_len, s);
+  std::shared_ptr<Block> Lnew = grow_left(Lold, nb, isoA, k0, env->nmode, env->I, s);
+  // the two-site problem of the pair (k+1, k+2)
+  auto B = std::make_unique<heff_blocks>();
+  B->ctx = ctx;
+  B->device = ctx->device;
+  B->stream = ctx->stream;
+  B->n_orb = n;
+  B->n_up = b->n_up;
+  B->n_dn = b->n_dn;
+  B->k0 = k0 + 1;
+  B->prec_mask = prec_mask;
+  B->env = env;
+  B->L = Lnew;
+  B->R = env->right[mR - 1];
+  build_psi_layout(*B);
+  build_terms(*B, env->I);
+  B->Ltmp.run(s);
+  B->Rtmp.run(s);
+  build_tasks(*B, s);
+  if (prec_mask & ((1u << HEFF_FP32) | (1u << HEFF_BF16X3))) {
+    const double* srcs[4] = {B->L->store.dev.as<double>(), B->Ltmp.tmp.dev.as<double>(),
+                             B->R->store.dev.as<double>(), B->Rtmp.tmp.dev.as<double>()};
+    int64_t sizes[4] = {B->L->store.total, B->Ltmp.tmp.total, B->R->store.total, B->Rtmp.tmp.total};
+    for (int i = 0; i < 4; ++i) {
+      B->f32[i].alloc((size_t)std::max<int64_t>(sizes[i], 1) * sizeof(float));
+      if (sizes[i]) HCHECK(launch_convert_f32(srcs[i], B->f32[i].as<float>(), sizes[i], s));
+    }
+  }
+  // StVec: one task per (new block, s_k)
+  const Iso& isoB = *env->riso[mR];  // site k+2: (site, right block of mR-1 sites) -> right block of mR sites
+  const Bond& blo = b->L->bond;      // old left bond (k sites)
+  const Bond& bro = b->R->bond;      // old right bond (mR sites)
+  const Bond& brn = B->R->bond;      // new right bond (mR - 1 sites)
+  ChainPlan P;
+  const int nbk = (int)B->blk_off.size();
+  for (int y = 0; y < nbk; ++y) {
+    const int qa2 = B->blk_qa[y], qg = B->blk_qb[y];
+    const int s1 = B->blk_desc[6 * y + 2], s2 = B->blk_desc[6 * y + 3];
+    const int qb = bro.find(brn.nu[qg] + SQU[s2], brn.nd[qg] + SQD[s2]);
+    Tile t{};
+    t.offOut = B->blk_off[y];
+    t.a = nb.dim[qa2];
+    t.e = brn.dim[qg];
+    t.ldOut = t.e;
+    t.t0 = (int32_t)P.tasks.size();
+    if (qb >= 0) {
+      const int64_t offR = isoB.block(s2, qb);
+      for (int sk = 0; sk < 4; ++sk) {
+        const int qa = blo.find(nb.nu[qa2] - SQU[sk], nb.nd[qa2] - SQD[sk]);
+        if (qa < 0) continue;
+        auto it = b->blk_index.find({qa, sk, s1});
+        if (it == b->blk_index.end()) continue;
+        const int x = it->second;
+        if (b->blk_qb[x] != qb) throw Error(HEFF_EINVAL, "internal: start vector block violates sector conservation");
+        const int64_t offL = isoA.block(sk, qa2);
+        if (offL < 0 || offR < 0) throw Error(HEFF_EINVAL, "internal: missing isometry block");
+        Task k{};
+        k.f = 1.0;
+        k.a = (uint16_t)nb.dim[qa2];
+        k.b = (uint16_t)blo.dim[qa];
+        k.c = (uint16_t)bro.dim[qb];
+        k.e = (uint16_t)brn.dim[qg];
+        k.offL = offL;  // A block stored D(q_a) x D'(q_a'): op(L) = A^T
+        k.ldL = (uint16_t)nb.dim[qa2];
+        k.offX = b->blk_off[x];
+        k.ldX = (uint16_t)bro.dim[qb];
+        k.offR = offR;  // B block stored D(q_g) x D(q_b) = e x c
+        k.ldR = (uint16_t)bro.dim[qb];
+        k.flags = (uint16_t)(T_TL | T_TR);
+        P.tasks.push_back(k);
+      }
+    }
+    t.t1 = (int32_t)P.tasks.size();
+    P.tiles.push_back(t);
+  }
+  B->start.alloc((size_t)std::max<int64_t>(B->n_elem, 1) * sizeof(double));
+  Bases<double> bs{};
+  bs.L[0] = bs.L[1] = isoA.dev.as<double>();
+  bs.X[0] = bs.X[1] = psi;
+  bs.R[0] = bs.R[1] = isoB.dev.as<double>();
+  bs.out = B->start.as<double>();
+  set_limits(bs, isoA.dev, isoA.dev, b->n_elem, isoB.dev, isoB.dev);
+  run_chain(P, bs, s);
+  HCHECK(hipStreamSynchronize(s));
+  *out = B.release();
+  if (trunc_out) *trunc_out = tr.release();
+  ABI_END(ctx)
+}
+
+extern "C" int heff_start_vector(const heff_blocks* b, const double** psi) {
+  if (!b || !psi) return HEFF_EINVAL;
+  if (!b->start.p) return HEFF_ESTATE;
+  *psi = b->start.as<double>();
+  return HEFF_OK;
+}
+
+// ---------------------------------------------------------------- mode rotation of the pair
+// The micro-iteration of the mode optimization (Sec. II.B, Fig. microiter):
+// the orbitals k and k+1 of the pair are rotated by
+// U = exp(theta (E_k,k+1 - E_k+1,k)) (the identity except for the 2 x 2
+// block), the new orbitals being c'+_i = sum_a U_ai c+_a.  The same
+// physical state then has the coefficients exp(-K) phi with K the
+// many-body generator sum_s (c+_ks c_k+1,s - c+_k+1,s c_ks); K acts on the
+// two middle sites only (the parity strings of the left block cancel in a
+// bilinear), so on the two-site vector it is one 16 x 16 matrix G(theta) =
+// exp(-theta K) on the middle index, block diagonal over the (n_up, n_dn)
+// of the two sites.  The integrals transform as h' = U^T h U and
+// V'_ijkl = sum U_ai U_bj U_ck U_dl V_abcd (heff_rotate_integrals), which
+// leaves <psi|H_eff|psi> unchanged.
+
+// matrix exponential of a 16 x 16 matrix by scaling and squaring with a
+// truncated Taylor series (the norm is scaled below 1/2; 20 terms)
+static Mat16 expm16(const Mat16& A) {
+  double nrm = 0.0;
+  for (int i = 0; i < 16; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < 16; ++j) r += std::fabs(A[i * 16 + j]);
+    nrm = std::max(nrm, r);
+  }
+  int sq = 0;
+  while (nrm > 0.5) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  Mat16 X = A;
+  const double sc = std::ldexp(1.0, -sq);
+  for (double& v : X) v *= sc;
+  Mat16 E = m16eye(), term = m16eye();
+  for (int k = 1; k <= 20; ++k) {
+    term = m16mul(term, X);
+    for (double& v : term) v /= (double)k;
+    m16axpy(E, 1.0, term);
+  }
+  for (int i = 0; i < sq; ++i) E = m16mul(E, E);
+  return E;
+}
+
+// G(theta) on the middle index 4 s_k + s_k+1
+static Mat16 pair_rotation(double theta, int k0) {
+  Mat16 K = m16zero();
+  for (int sg = 0; sg < 2; ++sg) {
+    const int a = 2 * k0 + sg, b = 2 * (k0 + 1) + sg;
+    m16axpy(K, 1.0, m16mul(mid_c(a, true, k0), mid_c(b, false, k0)));
+    m16axpy(K, -1.0, m16mul(mid_c(b, true, k0), mid_c(a, false, k0)));
+  }
+  for (double& v : K) v *= -theta;
+  Mat16 G = expm16(K);
+  // exact zeros outside the (n_up, n_dn) blocks of the two sites
+  for (int i = 0; i < 16; ++i)
+    for (int j = 0; j < 16; ++j) {
+      const int ui = SQU[i >> 2] + SQU[i & 3], di = SQD[i >> 2] + SQD[i & 3];
+      const int uj = SQU[j >> 2] + SQU[j & 3], dj = SQD[j >> 2] + SQD[j & 3];
+      if (ui != uj || di != dj) G[i * 16 + j] = 0.0;
+    }
+  return G;
+}
+
+static void rotate_pair(const heff_blocks* b, double theta, const double* psi, double* out, hipStream_t s) {
+  const Mat16 G = pair_rotation(theta, b->k0);
+  std::vector<RotJob> jobs;
+  const int nb = (int)b->blk_off.size();
+  for (int y = 0; y < nb; ++y) {
+    const int qa = b->blk_qa[y];
+    const int m2 = 4 * b->blk_desc[6 * y + 2] + b->blk_desc[6 * y + 3];
+    RotJob j{};
+    j.off_out = b->blk_off[y];
+    j.n = b->blk_desc[6 * y + 4] * b->blk_desc[6 * y + 5];
+    for (int m = 0; m < 16; ++m) {
+      const double g = G[m2 * 16 + m];
+      if (g == 0.0) continue;
+      auto it = b->blk_index.find({qa, m >> 2, m & 3});
+      if (it == b->blk_index.end()) continue;
+      if (j.nterm >= 4) throw Error(HEFF_EINVAL, "internal: more than four middle states in one sector");
+      if (b->blk_qb[it->second] != b->blk_qb[y]) throw Error(HEFF_EINVAL, "internal: rotation leaves the sector");
+      j.off_in[j.nterm] = b->blk_off[it->second];
+      j.c[j.nterm] = g;
+      ++j.nterm;
+    }
+    jobs.push_back(j);
+  }
+  DevBuf dj;
+  upload(dj, jobs, s);
+  HCHECK(launch_rotate_pair(dj.as<RotJob>(), (int64_t)jobs.size(), psi, out, s));
+  HCHECK(hipStreamSynchronize(s));
+}
+
+// S_1/2 = 2 ln sum sigma and S_1 = -sum lambda ln lambda of the normalized
+// state over the cut (left part | rest), from every singular value
+static void pair_entropies(heff_ctx* ctx, const heff_blocks* b, const double* psi, double* s_half, double* s_vn) {
+  heff_trunc* tr = nullptr;
+  if (int rc = heff_truncate(ctx, b, psi, INT32_MAX, &tr)) throw Error(rc, ctx->err);
+  std::unique_ptr<heff_trunc> t(tr);
+  double nrm2 = 0.0;
+  for (double v : t->sing) nrm2 += v * v;
+  if (!(nrm2 > 0.0)) throw Error(HEFF_EINVAL, "zero vector");
+  double sum = 0.0, svn = 0.0;
+  for (double v : t->sing) {
+    const double l = v * v / nrm2;
+    sum += v;
+    if (l > 0.0) svn -= l * std::log(l);
+  }
+  if (s_half) *s_half = 2.0 * std::log(sum / std::sqrt(nrm2));
+  if (s_vn) *s_vn = svn;
+}
+
+extern "C" int heff_rotate_pair(heff_ctx* ctx, const heff_blocks* b, double theta, const double* psi, double* out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out) throw Error(HEFF_EINVAL, "null argument");
+  if (psi == out) throw Error(HEFF_EINVAL, "psi and out alias");
+  if (!std::isfinite(theta)) throw Error(HEFF_EINVAL, "non-finite angle");
+  HCHECK(hipSetDevice(ctx->device));
+  rotate_pair(b, theta, psi, out, ctx->stream);
+  ABI_END(ctx)
+}
+
+extern "C" int heff_pair_entropy(heff_ctx* ctx, const heff_blocks* b, const double* psi, double* s_half, double* s_vn) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi) throw Error(HEFF_EINVAL, "null argument");
+  HCHECK(hipSetDevice(ctx->device));
+  pair_entropies(ctx, b, psi, s_half, s_vn);
+  ABI_END(ctx)
+}
+
+extern "C" int heff_optimize_pair(heff_ctx* ctx, const heff_blocks* b, const double* psi, double* out, double* theta,
+                                  double* s_before, double* s_after, int32_t* n_evals) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out || !theta) throw Error(HEFF_EINVAL, "null argument");
+  if (psi == out) throw Error(HEFF_EINVAL, "psi and out alias");
+  HCHECK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  int evals = 0;
+  auto f = [&](double t) {
+    rotate_pair(b, t, psi, out, s);
+    double sh = 0.0;
+    pair_entropies(ctx, b, out, &sh, nullptr);
+    ++evals;
+    return sh;
+  };
+  // S_1/2 has period pi in theta: 16 angles of [-pi/2, pi/2), then golden
+  // section on the bracket around the best one
+  const double pi = 3.14159265358979323846;
+  const int ng = 16;
+  double best_t = 0.0, best = 0.0;
+  for (int i = 0; i < ng; ++i) {
+    const double t = -pi / 2 + pi * i / ng, v = f(t);
+    if (i == 0 || v < best) {
+      best = v;
+      best_t = t;
+    }
+  }
+  const double hw = pi / ng, g = (std::sqrt(5.0) - 1.0) / 2.0;
+  double a = best_t - hw, bb = best_t + hw;
+  double c = bb - g * (bb - a), d = a + g * (bb - a);
+  double fc = f(c), fd = f(d);
+  while (bb - a > 1e-8) {
+    if (fc < fd) {
+      bb = d;
+      d = c;
+      fd = fc;
+      c = bb - g * (bb - a);
+      fc = f(c);
+    } else {
+      a = c;
+      c = d;
+      fc = fd;
+      d = a + g * (bb - a);
+      fd = f(d);
+    }
+  }
+  double t = 0.5 * (a + bb), st = f(t);
+  if (best < st) {
+    t = best_t;
+    st = f(t);
+  }
+  if (s_before) pair_entropies(ctx, b, psi, s_before, nullptr);
+  *theta = t;
+  if (s_after) *s_after = st;
+  if (n_evals) *n_evals = evals;
+  ABI_END(ctx)
+}
+
+extern "C" int heff_rotate_integrals(int32_t n, const double* h, const double* V, int32_t x, int32_t y, double theta,
+                                     double* h_out, double* V_out) {
+  if (n <= 0 || !h || !V || !h_out || !V_out || x < 0 || y < 0 || x >= n || y >= n || x == y) return HEFF_EINVAL;
+  if (!std::isfinite(theta)) return HEFF_EINVAL;
+  const double c = std::cos(theta), sn = std::sin(theta);
+  // U_aa = 1 (a != x, y); U_xx = U_yy = c, U_xy = s, U_yx = -s; new index i
+  // mixes old x and y through column i of U
+  auto mix = [&](double vx, double vy, int i) -> double {  // sum_a U_ai v_a over a in {x, y}
+    return i == x ? c * vx - sn * vy : sn * vx + c * vy;
+  };
+  const size_t N = (size_t)n;
+  std::vector<double> H(h, h + N * N);
+  for (int pass = 0; pass < 2; ++pass)  // h' = U^T h U: rotate the row, then the column index
+    for (size_t o = 0; o < N; ++o) {
+      auto at = [&](int i) -> double& { return pass == 0 ? H[(size_t)i * N + o] : H[o * N + (size_t)i]; };
+      const double vx = at(x), vy = at(y);
+      at(x) = mix(vx, vy, x);
+      at(y) = mix(vx, vy, y);
+    }
+  std::copy(H.begin(), H.end(), h_out);
+  std::vector<double> W(V, V + N * N * N * N);
+  const size_t st[4] = {N * N * N, N * N, N, 1};
+  for (int ax = 0; ax < 4; ++ax)  // one index of V at a time
+    for (size_t r = 0; r < N * N * N; ++r) {
+      // r enumerates the other three indices
+      size_t rem = r, base = 0;
+      for (int o = 3; o >= 0; --o) {
+        if (o == ax) continue;
+        base += (rem % N) * st[o];
+        rem /= N;
+      }
+      double& ex = W[base + (size_t)x * st[ax]];
+      double& ey = W[base + (size_t)y * st[ax]];
+      const double vx = ex, vy = ey;
+      ex = mix(vx, vy, x);
+      ey = mix(vx, vy, y);
+    }
+  std::copy(W.begin(), W.end(), V_out);
   return HEFF_OK;
 }
 

@@ -128,6 +128,16 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
 // split-precision (bf16 hi+lo, FP32 accumulation) product on the FP32 operand arenas
 hipError_t launch_bf16x3(const Tile* tiles, const WorkSet& ws, const Task* tasks, Bases<float> b,
                          const hipStream_t* s, hipEvent_t (*ev)[2] = nullptr);
+// Rotation of the two middle orbitals on a two-site vector: every output
+// block is a combination of at most four input blocks of the same shape
+// (the middle states of one (n_up, n_dn) sector of the two sites).
+struct RotJob {
+  int64_t off_out;
+  int64_t off_in[4];
+  double c[4];
+  int32_t n, nterm;  // elements of the block, terms used
+};
+hipError_t launch_rotate_pair(const RotJob* jobs, int64_t n_jobs, const double* in, double* out, hipStream_t s);
 // symmetric eigenproblems of the truncation (one work-group each, n <= kMaxEig)
 constexpr int kMaxEig = 1024;
 struct EigJob {

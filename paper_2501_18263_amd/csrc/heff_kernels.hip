@@ -1549,6 +1549,24 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t m, int64_t n, int
     }
 }
 
+// One work-group per output block of the pair rotation: out = sum_t c_t in_t
+// over the block's elements (contiguous, coalesced; HBM-bound).
+__global__ __launch_bounds__(256) void rotate_pair_kernel(const RotJob* __restrict__ jobs, const double* __restrict__ in,
+                                                          double* __restrict__ out) {
+  const RotJob j = jobs[blockIdx.x];
+  for (int i = threadIdx.x; i < j.n; i += 256) {
+    double v = 0.0;
+    for (int t = 0; t < j.nterm; ++t) v += j.c[t] * in[j.off_in[t] + i];
+    out[j.off_out + i] = v;
+  }
+}
+
+hipError_t launch_rotate_pair(const RotJob* jobs, int64_t n_jobs, const double* in, double* out, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rotate_pair_kernel, dim3((unsigned)n_jobs), dim3(256), 0, s, jobs, in, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_f64(int64_t m, int64_t n, int64_t k, const double* A, const double* B, double* C,
                            hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libheff.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
+KEEP_ENV = 1 << 8  # build flag: keep the environment of later sweep steps
 PREC_NAMES = {FP64: "fp64", FP32: "fp32", BF16X3: "bf16x3"}
 
 # operator kinds of heff_debug_op
@@ -127,6 +128,14 @@ _lib.heff_trunc_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POI
 _lib.heff_trunc_get.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _vp]
 _lib.heff_trunc_free.argtypes = [_vp]
+_lib.heff_sweep_right.argtypes = [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_uint32, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
+_lib.heff_start_vector.argtypes = [_vp, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+_lib.heff_rotate_pair.argtypes = [_vp, _vp, ctypes.c_double, _vp, _vp]
+_lib.heff_pair_entropy.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.heff_optimize_pair.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+_lib.heff_rotate_integrals.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       _vp, _vp]
 _lib.heff_batch_layout.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64)]
 _lib.heff_batch_create.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
@@ -154,6 +163,8 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_davidson_step", "heff_dav_ritz", "heff_dav_free", "heff_timing", "heff_timing_read",
             "heff_task_stats_variant", "heff_task_stats_issued", "heff_blocks_shard", "heff_energy", "heff_energy_backward",
             "heff_op_arena", "heff_energy_noalloc", "heff_kappa_gradient", "heff_integral_gradient", "heff_set_fp64_kernel", "heff_truncate", "heff_trunc_info", "heff_trunc_get", "heff_trunc_free",
+            "heff_sweep_right", "heff_start_vector", "heff_rotate_pair", "heff_pair_entropy",
+            "heff_optimize_pair", "heff_rotate_integrals",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
             "heff_batch_apply", "heff_batch_free")
 N_VARIANTS = 4
@@ -291,20 +302,46 @@ class _DeviceArray:
         self._owner = owner
 
 
+def _trunc_dict(ctx, h, device):
+    """Contents of a truncation result: dict(sing, discarded, tab
+    {(nu, nd): dim}, iso_flat (host copy of the isometry))."""
+    import torch
+    nk = ctypes.c_int32()
+    disc = ctypes.c_double()
+    ns = ctypes.c_int32()
+    ln = ctypes.c_int64()
+    _lib.heff_trunc_info(h, ctypes.byref(nk), ctypes.byref(disc), ctypes.byref(ns), ctypes.byref(ln))
+    sing = np.empty(nk.value)
+    nu = np.empty(ns.value, dtype=np.int32)
+    nd = np.empty(ns.value, dtype=np.int32)
+    dm = np.empty(ns.value, dtype=np.int32)
+    iso = torch.empty(max(ln.value, 1), dtype=torch.float64, device=device)
+    ctx.check(_lib.heff_trunc_get(ctx._h, h, sing.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  dm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(iso)))
+    flat = iso[: ln.value].cpu().numpy()
+    tab = {(int(a), int(b_)): int(d) for a, b_, d in zip(nu, nd, dm)}
+    return dict(sing=sing, discarded=disc.value, tab=tab, iso_flat=flat)
+
+
 class Blocks:
     """Renormalized operators + task table of one two-site problem."""
 
-    def __init__(self, ctx: Context, problem, precs=(FP64,)):
+    def __init__(self, ctx: Context, problem, precs=(FP64,), keep_env=False, _handle=None):
         self.ctx = ctx
-        keep = []
-        prob = _marshal(problem, keep)
-        mask = 0
-        for pr in precs:
-            mask |= 1 << pr
-        out = _vp()
-        ctx.check(_lib.heff_build_blocks(ctx._h, ctypes.byref(prob), mask, ctypes.byref(out)))
-        self._h = out
         self.precs = tuple(precs)
+        if _handle is not None:  # blocks made by a sweep step
+            out = _handle
+        else:
+            keep = []
+            prob = _marshal(problem, keep)
+            mask = KEEP_ENV if keep_env else 0
+            for pr in precs:
+                mask |= 1 << pr
+            out = _vp()
+            ctx.check(_lib.heff_build_blocks(ctx._h, ctypes.byref(prob), mask, ctypes.byref(out)))
+        self._h = out
         n = ctypes.c_int64()
         nb = ctypes.c_int32()
         desc = ctypes.POINTER(ctypes.c_int32)()
@@ -432,25 +469,71 @@ class Blocks:
         h = _vp()
         self.ctx.check(_lib.heff_truncate(self.ctx._h, self._h, _ptr(psi), int(d_keep), ctypes.byref(h)))
         try:
-            nk = ctypes.c_int32()
-            disc = ctypes.c_double()
-            ns = ctypes.c_int32()
-            ln = ctypes.c_int64()
-            _lib.heff_trunc_info(h, ctypes.byref(nk), ctypes.byref(disc), ctypes.byref(ns), ctypes.byref(ln))
-            sing = np.empty(nk.value)
-            nu = np.empty(ns.value, dtype=np.int32)
-            nd = np.empty(ns.value, dtype=np.int32)
-            dm = np.empty(ns.value, dtype=np.int32)
-            iso = torch.empty(max(ln.value, 1), dtype=torch.float64, device=psi.device)
-            self.ctx.check(_lib.heff_trunc_get(self.ctx._h, h, sing.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                               nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                               nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                               dm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(iso)))
-            flat = iso[: ln.value].cpu().numpy()
+            return _trunc_dict(self.ctx, h, psi.device)
         finally:
             _lib.heff_trunc_free(h)
-        tab = {(int(a), int(b_)): int(d) for a, b_, d in zip(nu, nd, dm)}
-        return dict(sing=sing, discarded=disc.value, tab=tab, iso_flat=flat)
+
+    def sweep_right(self, psi, d_keep, precs=None):
+        """One left-to-right sweep step from these blocks (built with
+        keep_env=True) and the optimized two-site vector psi (float64 device
+        tensor): truncation to d_keep states, Ren_l, the pair one site to the
+        right.  Returns (blocks of the new pair, its start vector as a float64
+        device tensor viewing memory owned by those blocks, truncation dict
+        as truncate())."""
+        import torch
+        if psi.dtype != torch.float64 or psi.numel() != self.n_elem or not psi.is_cuda:
+            raise ValueError("psi must be a float64 device tensor of %d elements" % self.n_elem)
+        precs = self.precs if precs is None else tuple(precs)
+        mask = 0
+        for pr in precs:
+            mask |= 1 << pr
+        out = _vp()
+        tr = _vp()
+        self.ctx.check(_lib.heff_sweep_right(self.ctx._h, self._h, _ptr(psi), int(d_keep), mask, ctypes.byref(out),
+                                             ctypes.byref(tr)))
+        try:
+            info = _trunc_dict(self.ctx, tr, psi.device)
+        finally:
+            _lib.heff_trunc_free(tr)
+        nb = Blocks(self.ctx, None, precs=precs, _handle=out)
+        sp = ctypes.POINTER(ctypes.c_double)()
+        self.ctx.check(_lib.heff_start_vector(out, ctypes.byref(sp)))
+        addr = ctypes.cast(sp, ctypes.c_void_p).value
+        start = torch.as_tensor(_DeviceArray(addr, nb.n_elem, "<f8", nb), device=psi.device)
+        return nb, start, info
+
+    def _check64(self, psi):
+        import torch
+        if psi.dtype != torch.float64 or psi.numel() != self.n_elem or not psi.is_cuda or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous float64 device tensor of %d elements" % self.n_elem)
+
+    def rotate_pair(self, psi, theta, out=None):
+        """The vector of the same state after the rotation of the pair's two
+        orbitals by theta (heff_rotate_pair)."""
+        import torch
+        self._check64(psi)
+        out = torch.empty_like(psi) if out is None else out
+        self.ctx.check(_lib.heff_rotate_pair(self.ctx._h, self._h, float(theta), _ptr(psi), _ptr(out)))
+        return out
+
+    def pair_entropy(self, psi):
+        """(S_1/2, S_1) of the left part of the normalized state psi."""
+        self._check64(psi)
+        sh, sv = ctypes.c_double(), ctypes.c_double()
+        self.ctx.check(_lib.heff_pair_entropy(self.ctx._h, self._h, _ptr(psi), ctypes.byref(sh), ctypes.byref(sv)))
+        return sh.value, sv.value
+
+    def optimize_pair(self, psi):
+        """Mode rotation of the pair minimizing S_1/2: (theta, rotated psi,
+        S_1/2 before, S_1/2 after, trials)."""
+        import torch
+        self._check64(psi)
+        out = torch.empty_like(psi)
+        th, sb, sa = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        ne = ctypes.c_int32()
+        self.ctx.check(_lib.heff_optimize_pair(self.ctx._h, self._h, _ptr(psi), _ptr(out), ctypes.byref(th),
+                                               ctypes.byref(sb), ctypes.byref(sa), ctypes.byref(ne)))
+        return th.value, out, sb.value, sa.value, ne.value
 
     def debug_op(self, side, kind, i=0, j=0):
         n = _lib.heff_debug_op(self._h, side, kind, i, j, None, 0)
@@ -577,6 +660,21 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def rotate_integrals(h, V, x, y, theta):
+    """(U^T h U, V rotated on all four indices) for the rotation of orbitals
+    (x, y) by theta (heff_rotate_integrals; host only)."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n = h.shape[0]
+    h2 = np.empty_like(h)
+    V2 = np.empty_like(V)
+    rc = _lib.heff_rotate_integrals(n, h.ctypes.data, V.ctypes.data, int(x), int(y), float(theta),
+                                    h2.ctypes.data, V2.ctypes.data)
+    if rc != 0:
+        raise HeffError(rc, "heff_rotate_integrals failed")
+    return h2, V2
 
 
 def kappa_gradient(ctx: Context, problem, psi, pairs):

@@ -30,3 +30,15 @@ def layout_matches(p, blocks):
         if (qa, sk, sk1, da, db, off) != ((u, d), s1, s2, r, c, o):
             return False
     return True
+
+
+def iso_blocks(new_tab, old_tab, flat):
+    """{q_out: stacked matrix} of a flat isometry in the library's layout
+    (per out-sector, rows stacked by site state s = 0..3, row-major)."""
+    out, off = {}, 0
+    for q, d in new_tab.items():
+        rows = sum(old_tab.get((q[0] - synth.SITE_Q[s][0], q[1] - synth.SITE_Q[s][1]), 0) for s in range(4))
+        out[q] = np.asarray(flat[off: off + rows * d]).reshape(rows, d)
+        off += rows * d
+    assert off == len(flat)
+    return out

@@ -1,9 +1,11 @@
 // Driver of the CPU host check (test infrastructure only): reads two-site
 // problems from a file written by tests/test_hostcheck.py, runs the
 // library's C ABI on them with the host-only runtime (build of the blocks
-// and task tables with FP32 operands, single products in both precisions,
-// the diagonal, and a batch of all problems with plain and graph-replayed
-// launches), and reports what the launch checkers found.
+// and task tables with FP32 operands, single products in every precision,
+// the diagonal, a sweep step to the next pair with its product and the mode
+// rotation of that pair (rotation, entropies, angle search), and a batch
+// of all problems with plain and graph-replayed launches), and reports what
+// the launch checkers found.
 //
 // Problem file (little endian): "HEFFPRB1", int32 count, then per problem
 // int32 n_orb, n_up, n_dn; double h[n^2]; double V[n^4];
@@ -132,7 +134,8 @@ int main(int argc, char** argv) {
   int64_t n_tasks = 0;
   for (int i = 0; i < count; ++i) {
     heff_blocks* b = nullptr;
-    rc = heff_build_blocks(ctx, &probs[i]->p, (1u << HEFF_FP32) | (1u << HEFF_BF16X3), &b);
+    rc = heff_build_blocks(ctx, &probs[i]->p, (1u << HEFF_FP32) | (1u << HEFF_BF16X3) | (single ? HEFF_KEEP_ENV : 0u),
+                           &b);
     if (rc) return fail(ctx, ("heff_build_blocks of problem " + std::to_string(i)).c_str(), rc);
     int64_t ne = 0, nt = 0;
     int32_t nb = 0;
@@ -154,6 +157,30 @@ int main(int argc, char** argv) {
       if ((rc = heff_apply(ctx, b, HEFF_FP32, x, y))) return fail(ctx, "heff_apply FP32", rc);
       if ((rc = heff_apply(ctx, b, HEFF_BF16X3, x, y))) return fail(ctx, "heff_apply BF16X3", rc);
       if ((rc = heff_diag(ctx, b, (double*)y))) return fail(ctx, "heff_diag", rc);
+      if (probs[i]->n - (probs[i]->n / 2 - 1) - 2 >= 1) {  // a sweep step to the next pair, then its product
+        heff_blocks* b2 = nullptr;
+        heff_trunc* tr = nullptr;
+        if ((rc = heff_sweep_right(ctx, b, (const double*)x, 24, 1u, &b2, &tr))) return fail(ctx, "heff_sweep_right", rc);
+        const double* st = nullptr;
+        if ((rc = heff_start_vector(b2, &st))) return fail(ctx, "heff_start_vector", rc);
+        int64_t ne2 = 0;
+        int32_t nb2 = 0;
+        heff_psi_layout(b2, &ne2, &nb2, &desc, &off);
+        void* y2 = nullptr;
+        hipMalloc(&y2, (size_t)ne2 * 8);
+        if ((rc = heff_apply(ctx, b2, HEFF_FP64, st, y2))) return fail(ctx, "heff_apply after the sweep step", rc);
+        double th = 0.0, sb = 0.0, sa = 0.0, sh = 0.0, sv = 0.0;
+        int32_t ne_ = 0;
+        if ((rc = heff_rotate_pair(ctx, b2, 0.3, st, (double*)y2))) return fail(ctx, "heff_rotate_pair", rc);
+        // no arithmetic runs here, so the vectors are zero and the entropies
+        // refuse them (HEFF_EINVAL) after the rotation and SVD launches
+        if ((rc = heff_pair_entropy(ctx, b2, st, &sh, &sv)) && rc != HEFF_EINVAL) return fail(ctx, "heff_pair_entropy", rc);
+        if ((rc = heff_optimize_pair(ctx, b2, st, (double*)y2, &th, &sb, &sa, &ne_)) && rc != HEFF_EINVAL)
+          return fail(ctx, "heff_optimize_pair", rc);
+        hipFree(y2);
+        heff_trunc_free(tr);
+        heff_blocks_free(b2);
+      }
       hipFree(x);
       hipFree(y);
     }

@@ -349,6 +349,18 @@ hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks
   });
 }
 
+hipError_t launch_rotate_pair(const RotJob* jobs, int64_t n_jobs, const double* in, double* out, hipStream_t) {
+  return hc::run([=]() {
+    if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(RotJob), "rotation jobs")) return;
+    for (int64_t i = 0; i < n_jobs; ++i) {
+      const RotJob j = jobs[i];
+      if (j.nterm < 0 || j.nterm > 4) hc::violation("rotation job %lld: %d terms", (long long)i, j.nterm);
+      hc::check_range(out + j.off_out, (size_t)j.n * 8, "rotation output block");
+      for (int t = 0; t < j.nterm && t < 4; ++t) hc::check_range(in + j.off_in[t], (size_t)j.n * 8, "rotation input block");
+    }
+  });
+}
+
 hipError_t launch_gemm_f64(int64_t m, int64_t n, int64_t k, const double* A, const double* B, double* C,
                            hipStream_t) {
   return hc::run([=]() {
