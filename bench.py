@@ -535,6 +535,74 @@ def bench_shards(args):
            "flop_imbalance": max(q["flops"] for q in ranks) / (F / args.shards), "ranks": ranks}
     print(json.dumps(out), flush=True)
 
+def bench_sweep(args):
+    """The phases around Diag_H at the benchmark's size (Sec. IV.A names
+    SVD, Ren_l and StVec): one left-to-right sweep step (truncation to D,
+    the left block grown by site k with the truncated isometry, the task
+    table of the next pair, its start vector) and the mode-optimization
+    micro-iteration of the pair (angle search over S_1/2, one SVD per
+    trial), each timed around a device-wide synchronization; the SVD alone
+    is timed separately.  The two-site vector is the benchmark's random
+    start vector (the timings do not depend on its values)."""
+    import torch
+
+    from paper_2501_18263_amd import heff, synth
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    p = synth.make_problem(args.n_orb, args.d, args.seed, beta=args.beta)
+    ctx = heff.Context(0)
+    t0 = time.perf_counter()
+    B = heff.Blocks(ctx, p, keep_env=True)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    x = torch.tensor(synth.random_psi(p), device="cuda")
+    y = torch.empty_like(x)
+    B.apply(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.apply(x, y)
+    torch.cuda.synchronize()
+    t_prod = time.perf_counter() - t0
+    out = {}
+    svd_s = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = B.truncate(x, args.d)
+        svd_s.append(time.perf_counter() - t0)
+    out["svd_s"] = sorted(svd_s)[len(svd_s) // 2]
+    log("SVD (truncation to %d): %.3f s" % (args.d, out["svd_s"]))
+    step_s = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B2, start, info = B.sweep_right(x, args.d)
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t0)
+        n2, st2 = B2.n_elem, B2.stats()
+        B2.close()
+    out["sweep_step_s"] = sorted(step_s)[len(step_s) // 2]
+    out["ren_l_tables_stvec_s"] = out["sweep_step_s"] - out["svd_s"]
+    out["next_pair"] = {"psi_dim": n2, "tasks": st2["n_tasks"], "flops_per_product": st2["flops"],
+                        "discarded_weight": info["discarded"]}
+    log("sweep step: %.3f s (SVD %.3f, Ren_l + tables + StVec %.3f)" % (
+        out["sweep_step_s"], out["svd_s"], out["ren_l_tables_stvec_s"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, xr, sb, sa, ne = B.optimize_pair(x)
+    torch.cuda.synchronize()
+    out["mode_micro_iteration"] = {"seconds": time.perf_counter() - t0, "trials": ne, "theta": th,
+                                   "S_half_before": sb, "S_half_after": sa}
+    log("mode micro-iteration: %.3f s, %d trials, S_1/2 %.6f -> %.6f" % (out["mode_micro_iteration"]["seconds"], ne, sb, sa))
+    res = {"metric": "sweep step and mode micro-iteration around Diag_H, N=%d D=%d" % (args.n_orb, args.d),
+           "value": out["sweep_step_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": 1e3 * out["sweep_step_s"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "one sweep step and one mode micro-iteration, N=%d D=%d beta=%g" % (
+               args.n_orb, args.d, args.beta), "build_s": t_build, "product_s": t_prod},
+           "details": out}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -546,7 +614,7 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precs", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "backward", "shards"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "backward", "shards", "sweep"], default="single")
     ap.add_argument("--shards", type=int, default=8)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--converge", type=int, default=500,
@@ -599,6 +667,9 @@ def main():
         return
     if args.workload == "shards":
         bench_shards(args)
+        return
+    if args.workload == "sweep":
+        bench_sweep(args)
         return
 
     cb_proc = None if args.no_cpu_baseline else cpu_baseline_start()  # before the GPU is touched

@@ -2194,6 +2194,17 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
       roff[q][sk] = nrow[q];
       if (qa >= 0) nrow[q] += bl.dim[qa];
     }
+  // columns of M_Q' (s_k+1, q_beta); M has rank at most min(rows, columns),
+  // so the remaining eigenvalues of M M^T are zero by dimension (their
+  // computed values are rounding, about 1e-17, whose square roots would
+  // otherwise enter the singular values at the 1e-9 level)
+  const Bond& br = b->R->bond;
+  std::vector<int> ncol(nq, 0);
+  for (int q = 0; q < nq; ++q)
+    for (int s1 = 0; s1 < 4; ++s1) {
+      const int qb = br.find(b->n_up - qlist[q].first - SQU[s1], b->n_dn - qlist[q].second - SQD[s1]);
+      if (qb >= 0) ncol[q] += br.dim[qb];
+    }
   std::vector<int64_t> moff(nq);
   int64_t mtot = 0;
   for (int q = 0; q < nq; ++q) {
@@ -2271,6 +2282,7 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
     ord[q].resize(nrow[q]);
     for (int i = 0; i < nrow[q]; ++i) ord[q][i] = i;
     std::stable_sort(ord[q].begin(), ord[q].end(), [&](int x, int y) { return lam[q][x] > lam[q][y]; });
+    for (int r = std::min(nrow[q], ncol[q]); r < nrow[q]; ++r) lam[q][ord[q][r]] = 0.0;
     for (int r = 0; r < nrow[q]; ++r) all.push_back({lam[q][ord[q][r]], q, r});
   }
   std::stable_sort(all.begin(), all.end(), [](const Cand& x, const Cand& y) {
