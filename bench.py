@@ -95,9 +95,21 @@ def write_traffic_record(args):
     import numpy as np
     d = args.traffic_record
     kern = args.traffic_kernel
-    fetch = [v for _, v, _ in _counter_rows(os.path.join(d, "fetch"), "FETCH_SIZE", kern)]
-    write = [v for _, v, _ in _counter_rows(os.path.join(d, "write"), "WRITE_SIZE", kern)]
-    grid = [g for _, _, g in _counter_rows(os.path.join(d, "fetch"), "FETCH_SIZE", kern)]
+    # the product launches: the dispatches with the grid of the run's last
+    # one whose fetch is at least half the largest (the block build launches
+    # the same kernel first, on small blocks, some with the same grid)
+    fr = _counter_rows(os.path.join(d, "fetch"), "FETCH_SIZE", kern)
+    wr = _counter_rows(os.path.join(d, "write"), "WRITE_SIZE", kern)
+    if not (fr and wr):
+        raise SystemExit("missing counter rows for %s" % kern)
+    g_last = fr[-1][2]
+    fmax = max(v for _, v, g in fr if g == g_last)
+    prod_ids = [i for i, v, g in fr if g == g_last and v >= 0.5 * fmax]
+    fetch = [v for i, v, g in fr if i in prod_ids]
+    # WRITE_SIZE comes from a second run with the same dispatch sequence
+    wids = [i for i, _, g in wr if g == g_last]
+    write = [v for i, v, g in wr if g == g_last and i in wids[-len(prod_ids):]]
+    grid = [g_last]
     cf = [v for _, v, _ in _counter_rows(os.path.join(d, "cfetch"), "FETCH_SIZE", "copyBuffer")]
     cw = [v for _, v, _ in _counter_rows(os.path.join(d, "cwrite"), "WRITE_SIZE", "copyBuffer")]
     if not (fetch and write and cf and cw):
