@@ -196,9 +196,11 @@ int heff_diag(heff_ctx* ctx, const heff_blocks* b, double* diag);
 /* Truncation (the SVD step after Diag_H; Sec. II.A keeps the D largest
  * singular values).  Psi (device, n_elem doubles) is reshaped per sector Q'
  * of the enlarged left block L + {k} into M[(s_k, alpha), (s_k+1, beta)];
- * the squared singular values and left singular vectors are taken as the
- * eigenpairs of M M^T (FP64 Jacobi on the device); the d_keep largest over
- * all sectors are kept (ties: sector order, then rank).  The result object
+ * its singular values and left singular vectors come from a block one-sided
+ * (Hestenes) Jacobi SVD of M itself in FP64 on the device (rows rotated in
+ * pairs of 16-row blocks until mutually orthogonal to 1e-15; singular values
+ * are the row norms, which keeps small ones accurate); the d_keep largest
+ * over all sectors are kept (ties: sector order, then rank).  The result object
  * holds the kept singular values (descending), the discarded weight (sum of
  * the other squared singular values), the new bond table of the block
  * L + {k} and the new left isometry of site k on the device in the layout of

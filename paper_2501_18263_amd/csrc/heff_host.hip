@@ -2205,75 +2205,126 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
       const int qb = br.find(b->n_up - qlist[q].first - SQU[s1], b->n_dn - qlist[q].second - SQD[s1]);
       if (qb >= 0) ncol[q] += br.dim[qb];
     }
-  std::vector<int64_t> moff(nq);
-  int64_t mtot = 0;
+  // dense M_Q' (B, m x c) and W^T = I (m x m) per sector
+  std::vector<int64_t> boff(nq), woff(nq), soff(nq);
+  int64_t btot = 0, wtot = 0, stot = 0;
   for (int q = 0; q < nq; ++q) {
-    if (nrow[q] > kMaxEig) throw Error(HEFF_EINVAL, "enlarged sector larger than the eigensolver limit");
-    moff[q] = mtot;
-    mtot += (int64_t)nrow[q] * nrow[q];
+    boff[q] = btot;
+    woff[q] = wtot;
+    soff[q] = stot;
+    btot += (int64_t)nrow[q] * ncol[q];
+    wtot += (int64_t)nrow[q] * nrow[q];
+    stot += nrow[q];
   }
-  // rho_Q'[(s,a),(s',a')] = sum_{s1} Psi(a, s, s1) Psi(a', s', s1)^T
-  ChainPlan P;
+  std::vector<std::array<int, 4>> coff(nq);  // per sector, per s_k+1: column offset
+  for (int q = 0; q < nq; ++q) {
+    int c = 0;
+    for (int s1 = 0; s1 < 4; ++s1) {
+      coff[q][s1] = c;
+      const int qb = br.find(b->n_up - qlist[q].first - SQU[s1], b->n_dn - qlist[q].second - SQD[s1]);
+      if (qb >= 0) c += br.dim[qb];
+    }
+  }
+  std::vector<CopyJob> cj;
   for (int q = 0; q < nq; ++q)
-    for (int si = 0; si < 4; ++si) {
-      int qa = rq[q][si];
+    for (int sk = 0; sk < 4; ++sk) {
+      const int qa = rq[q][sk];
       if (qa < 0) continue;
-      for (int sj = 0; sj < 4; ++sj) {
-        int qa2 = rq[q][sj];
-        if (qa2 < 0) continue;
-        Tile t{};
-        t.offOut = moff[q] + (int64_t)roff[q][si] * nrow[q] + roff[q][sj];
-        t.a = bl.dim[qa];
-        t.e = bl.dim[qa2];
-        t.ldOut = nrow[q];
-        t.t0 = (int32_t)P.tasks.size();
-        for (int s1 = 0; s1 < 4; ++s1) {
-          auto ix = b->blk_index.find({qa, si, s1});
-          auto iy = b->blk_index.find({qa2, sj, s1});
-          if (ix == b->blk_index.end() || iy == b->blk_index.end()) continue;
-          const int x = ix->second, y = iy->second;
-          const int c = b->blk_desc[6 * x + 5];
-          Task k{};
-          k.f = 1.0;
-          k.offL = b->blk_off[x];
-          k.offR = b->blk_off[y];
-          k.a = (uint16_t)bl.dim[qa];
-          k.b = k.c = (uint16_t)c;
-          k.e = (uint16_t)bl.dim[qa2];
-          k.ldL = (uint16_t)c;
-          k.ldR = (uint16_t)c;
-          k.flags = (uint16_t)(T_IDX | T_TR);
-          P.tasks.push_back(k);
-        }
-        t.t1 = (int32_t)P.tasks.size();
-        P.tiles.push_back(t);
+      for (int s1 = 0; s1 < 4; ++s1) {
+        auto it = b->blk_index.find({qa, sk, s1});
+        if (it == b->blk_index.end()) continue;
+        const int x = it->second;
+        CopyJob j{};
+        j.src = b->blk_off[x];
+        j.dst = boff[q] + (int64_t)roff[q][sk] * ncol[q] + coff[q][s1];
+        j.rows = b->blk_desc[6 * x + 4];
+        j.cols = b->blk_desc[6 * x + 5];
+        j.ld = ncol[q];
+        cj.push_back(j);
       }
     }
-  DevBuf rho, vec;
-  rho.alloc((size_t)std::max<int64_t>(mtot, 1) * sizeof(double));
-  vec.alloc((size_t)std::max<int64_t>(mtot, 1) * sizeof(double));
-  Bases<double> bs{};
-  bs.L[0] = bs.L[1] = psi;
-  bs.R[0] = bs.R[1] = psi;
-  bs.X[0] = bs.X[1] = psi;
-  bs.out = rho.as<double>();
-  run_chain(P, bs, s);
-  std::vector<EigJob> jobs;
-  std::vector<int> job_q;
-  for (int q = 0; q < nq; ++q)
-    if (nrow[q] > 0) { jobs.push_back({moff[q], nrow[q], 0}); job_q.push_back(q); }
-  DevBuf djobs;
-  upload(djobs, jobs, s);
-  HCHECK(launch_sym_jacobi(djobs.as<EigJob>(), (int)jobs.size(), rho.as<double>(), vec.as<double>(), s));
-  // eigenvalues = diagonals
+  DevBuf Bm, WT, dcj, dwoff, dboff, dsoff, dm, dc, doff, dsig;
+  Bm.alloc((size_t)std::max<int64_t>(btot, 1) * sizeof(double));
+  WT.alloc((size_t)std::max<int64_t>(wtot, 1) * sizeof(double));
+  // columns of M without a psi block stay zero
+  if (btot) HCHECK(hipMemsetAsync(Bm.p, 0, (size_t)btot * sizeof(double), s));
+  upload(dcj, cj, s);
+  HCHECK(launch_copy_blocks(dcj.as<CopyJob>(), (int)cj.size(), psi, Bm.as<double>(), s));
+  upload(dwoff, woff, s);
+  upload(dboff, boff, s);
+  upload(dsoff, soff, s);
+  upload(dm, nrow, s);
+  upload(dc, ncol, s);
+  HCHECK(launch_identity(dwoff.as<int64_t>(), dm.as<int32_t>(), nq, WT.as<double>(), s));
+  // a row of B whose norm is below eps (m + c) ||M_Q'||_F is rounding of a
+  // zero singular value and takes no part in the rotations
+  dsig.alloc((size_t)std::max<int64_t>(stot, 1) * sizeof(double));
+  HCHECK(launch_row_norms(dboff.as<int64_t>(), dm.as<int32_t>(), dc.as<int32_t>(), dsoff.as<int64_t>(), nq,
+                          Bm.as<double>(), dsig.as<double>(), s));
+  std::vector<double> sig(stot);
+  if (stot) HCHECK(hipMemcpyAsync(sig.data(), dsig.p, (size_t)stot * sizeof(double), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  std::vector<double> small2(nq, 0.0);
+  for (int q = 0; q < nq; ++q) {
+    double f2 = 0.0;
+    for (int i = 0; i < nrow[q]; ++i) f2 += sig[soff[q] + i] * sig[soff[q] + i];
+    const double z = 2.220446049250313e-16 * (nrow[q] + ncol[q]);
+    small2[q] = z * z * f2;
+  }
+  // rounds of the block pair schedule, sweeps until every sector's rows are
+  // orthogonal to rounding: |G_ij| <= eps sqrt(c) sqrt(G_ii G_jj), c the
+  // length of a row (the one-sided Jacobi threshold of Demmel and Veselic)
+  std::vector<BjJob> bj;
+  int maxK = 0;
+  for (int q = 0; q < nq; ++q) {
+    if (nrow[q] < 2 || ncol[q] == 0) continue;
+    const int nbk = (nrow[q] + kBjRows - 1) / kBjRows;
+    const int K = nbk + (nbk & 1);
+    if (K < 2) continue;
+    maxK = std::max(maxK, K);
+    for (int pr = 0; pr < K / 2; ++pr) {
+      BjJob j{};
+      j.b_off = boff[q];
+      j.w_off = woff[q];
+      j.m = nrow[q];
+      j.c = ncol[q];
+      j.K = K;
+      j.pr = pr;
+      j.sector = q;
+      j.small2 = small2[q];
+      bj.push_back(j);
+    }
+  }
+  DevBuf dbj;
+  upload(dbj, bj, s);
+  doff.alloc((size_t)std::max(nq, 1) * sizeof(unsigned long long));
+  const double tol = 2.220446049250313e-16;
+  std::vector<unsigned long long> offbits(nq);
+  for (int sweep = 0; sweep < 40 && !bj.empty(); ++sweep) {
+    HCHECK(hipMemsetAsync(doff.p, 0, (size_t)nq * sizeof(unsigned long long), s));
+    for (int r = 0; r < maxK - 1; ++r)
+      HCHECK(launch_bj_round(dbj.as<BjJob>(), (int)bj.size(), Bm.as<double>(), WT.as<double>(),
+                             doff.as<unsigned long long>(), r, tol, s));
+    HCHECK(hipMemcpyAsync(offbits.data(), doff.p, (size_t)nq * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    bool done = true;
+    for (int q = 0; q < nq; ++q) {
+      double d;
+      std::memcpy(&d, &offbits[q], sizeof(d));
+      if (d > tol * std::sqrt((double)ncol[q])) done = false;
+    }
+    if (done) break;
+  }
+  // singular values: row norms of B (at most min(rows, columns) non-zero)
+  HCHECK(launch_row_norms(dboff.as<int64_t>(), dm.as<int32_t>(), dc.as<int32_t>(), dsoff.as<int64_t>(), nq,
+                          Bm.as<double>(), dsig.as<double>(), s));
+  if (stot) HCHECK(hipMemcpyAsync(sig.data(), dsig.p, (size_t)stot * sizeof(double), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
   std::vector<std::vector<double>> lam(nq);
   for (int q = 0; q < nq; ++q) {
     lam[q].resize(nrow[q]);
-    if (nrow[q] == 0) continue;
-    HCHECK(hipMemcpy2DAsync(lam[q].data(), sizeof(double), rho.as<double>() + moff[q], (size_t)(nrow[q] + 1) * sizeof(double),
-                            sizeof(double), nrow[q], hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < nrow[q]; ++i) lam[q][i] = sig[soff[q] + i] * sig[soff[q] + i];
   }
-  HCHECK(hipStreamSynchronize(s));
   // descending order inside each sector, then the global selection
   std::vector<std::vector<int>> ord(nq);
   struct Cand { double lam; int q, rank; };
@@ -2302,21 +2353,20 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
     }
   }
   T->n_kept = nk;
-  // new isometry: kept eigenvectors (descending) of every kept sector
+  // new isometry: kept left singular vectors (descending) of every kept sector
   std::vector<GatherJob> gj;
   std::vector<int32_t> cols;
   std::vector<size_t> col_start;
   int64_t ioff = 0;
-  for (size_t j = 0; j < jobs.size(); ++j) {
-    int q = job_q[j];
-    if (kept[q] == 0) continue;
+  for (int q = 0; q < nq; ++q) {
+    if (nrow[q] == 0 || kept[q] == 0) continue;
     T->nup.push_back(qlist[q].first);
     T->ndn.push_back(qlist[q].second);
     T->dim.push_back(kept[q]);
     col_start.push_back(cols.size());
     for (int r = 0; r < kept[q]; ++r) cols.push_back(ord[q][r]);
     GatherJob g{};
-    g.v_off = moff[q];
+    g.v_off = woff[q];
     g.out_off = ioff;
     g.n = nrow[q];
     g.ncol = kept[q];
@@ -2329,7 +2379,7 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
   upload(dg, gj, s);
   T->iso.alloc((size_t)std::max<int64_t>(ioff, 1) * sizeof(double));
   T->iso_len = ioff;
-  HCHECK(launch_gather_columns(dg.as<GatherJob>(), (int)gj.size(), vec.as<double>(), T->iso.as<double>(), s));
+  HCHECK(launch_gather_rows(dg.as<GatherJob>(), (int)gj.size(), WT.as<double>(), T->iso.as<double>(), s));
   HCHECK(hipStreamSynchronize(s));
   *out = T.release();
   ABI_END(ctx)

@@ -138,20 +138,47 @@ struct RotJob {
   int32_t n, nterm;  // elements of the block, terms used
 };
 hipError_t launch_rotate_pair(const RotJob* jobs, int64_t n_jobs, const double* in, double* out, hipStream_t s);
-// symmetric eigenproblems of the truncation (one work-group each, n <= kMaxEig)
-constexpr int kMaxEig = 1024;
-struct EigJob {
-  int64_t off;  // element offset of the n x n matrix (and of its eigenvectors)
-  int32_t n;
-  int32_t pad;
-};
 struct GatherJob {
   int64_t v_off, out_off;
-  const int32_t* cols;  // device array of ncol eigenvector column indices
+  const int32_t* cols;  // device array of ncol row indices of W^T
   int32_t n, ncol;
 };
-hipError_t launch_sym_jacobi(const EigJob* jobs, int n_jobs, double* A, double* V, hipStream_t s);
-hipError_t launch_gather_columns(const GatherJob* jobs, int n_jobs, const double* V, double* out, hipStream_t s);
+// Truncation SVD by block one-sided (Hestenes) Jacobi: per sector the rows
+// of B (m x c, row-major, a copy of M) and of W^T (m x m, starting as the
+// identity) are rotated together, two blocks of kBjRows rows at a time,
+// until the rows of B are mutually orthogonal; then M = W B, the singular
+// values are the row norms of B and the left singular vectors the rows of
+// W^T.  One job = one block pair of one sector in every round of the
+// round-robin schedule over the sector's K (even) blocks.
+constexpr int kBjRows = 16;
+struct BjJob {
+  int64_t b_off, w_off;  // element offsets of the sector's B and W^T
+  int32_t m, c;          // rows, columns of M
+  int32_t K, pr;         // blocks of the schedule (even), pair index in a round
+  int32_t sector, pad;
+  double small2;         // rows of B with squared norm <= small2 count as zero
+};
+// one round r of every job's schedule; off_max[sector] receives (as bits of
+// a non-negative double, atomic max) the largest |G_ij| / sqrt(G_ii G_jj)
+// of the round's Gram matrices; pairs already below tol * sqrt(c) are left unrotated
+hipError_t launch_bj_round(const BjJob* jobs, int n_jobs, double* B, double* WT, unsigned long long* off_max, int r,
+                           double tol, hipStream_t s);
+// B blocks of the truncation: copy psi block (rows x cols, contiguous) to
+// dst (row stride ld)
+struct CopyJob {
+  int64_t src, dst;
+  int32_t rows, cols, ld, pad;
+};
+hipError_t launch_copy_blocks(const CopyJob* jobs, int n_jobs, const double* src, double* dst, hipStream_t s);
+// W^T = identity for every sector (n_sect sectors: offsets woff, sizes m)
+hipError_t launch_identity(const int64_t* woff, const int32_t* m, int n_sect, double* WT, hipStream_t s);
+// sig[soff[q] + i] = norm of row i of sector q's B
+hipError_t launch_row_norms(const int64_t* boff, const int32_t* m, const int32_t* c, const int64_t* soff, int n_sect,
+                            const double* B, double* sig, hipStream_t s);
+// out[out_off + r * ncol + j] = sign_j * WT[w_off + rows_j * n + r]: kept
+// left singular vectors as isometry columns, each signed so that its
+// largest-magnitude entry is positive (GatherJob.cols holds row indices of W^T)
+hipError_t launch_gather_rows(const GatherJob* jobs, int n_jobs, const double* WT, double* out, hipStream_t s);
 hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0,
                        const double* L1, const double* R0, const double* R1, double* out,
                        hipStream_t s);

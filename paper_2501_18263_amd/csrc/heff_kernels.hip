@@ -1365,120 +1365,271 @@ hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ symmetric eigensolver (truncation)
-// One work-group per symmetric matrix A (n x n, row-major in global memory,
-// n <= kMaxEig): parallel cyclic Jacobi with the round-robin pair schedule;
-// on exit A's diagonal holds the eigenvalues and V the eigenvectors
-// (columns).  Sweeps stop when the off-diagonal Frobenius norm is below
-// 1e-15 of the total norm (at most 60 sweeps).
+// ------------------------------------------------------------------ truncation SVD (block one-sided Jacobi)
+// One work-group per (sector, block pair) of a round.  The pair's rows
+// (at most 2 kBjRows) of B are read in chunks of 64 columns through LDS to
+// form their Gram matrix G; G's eigenvectors Q come from a cyclic Jacobi in
+// LDS; the rows of B and of W^T are replaced by Q^T times themselves, which
+// makes the pair's rows of B mutually orthogonal.  All sums are in a fixed
+// order (bitwise reproducible).
+namespace bjk {
+constexpr int R2 = 2 * kBjRows;  // rows of a pair
+constexpr int CH = 64;           // columns per chunk
 
-__global__ __launch_bounds__(256) void sym_jacobi_kernel(const EigJob* __restrict__ jobs, double* __restrict__ A_all,
-                                                         double* __restrict__ V_all) {
-  __shared__ double cs[kMaxEig / 2], sn[kMaxEig / 2];
-  __shared__ int pp[kMaxEig / 2], qq[kMaxEig / 2];
-  __shared__ double red[256];
-  __shared__ int done;
-  const EigJob J = jobs[blockIdx.x];
-  const int n = J.n;
-  double* A = A_all + J.off;
-  double* V = V_all + J.off;
-  const int tid = threadIdx.x;
-  for (int64_t idx = tid; idx < (int64_t)n * n; idx += 256) V[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
-  __syncthreads();
-  const int K = (n + 1) & ~1;
-  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int64_t idx = tid; idx < (int64_t)n * n; idx += 256) {
-      const double a = A[idx];
-      tot += a * a;
-      if (idx / n != idx % n) off += a * a;
-    }
-    red[tid] = off;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) done = (offs <= 1e-30 * red[0]) ? 1 : 0;
-    __syncthreads();
-    if (done) break;
-    for (int r = 0; r < K - 1; ++r) {
-      for (int pr = tid; pr < K / 2; pr += 256) {
-        const int a = (pr == 0) ? 0 : 1 + ((pr - 1 + r) % (K - 1));
-        const int bq = 1 + ((K - 1 - pr - 1 + r) % (K - 1));
-        const int p = a < bq ? a : bq, q = a < bq ? bq : a;
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[(int64_t)p * n + q];
-          if (apq != 0.0) {
-            const double th = (A[(int64_t)q * n + q] - A[(int64_t)p * n + p]) / (2.0 * apq);
-            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-          }
-        }
-        cs[pr] = c;
-        sn[pr] = s;
-        pp[pr] = p;
-        qq[pr] = q < n ? q : p;
-      }
-      __syncthreads();
-      for (int64_t idx = tid; idx < (int64_t)(K / 2) * n; idx += 256) {
-        const int pr = (int)(idx / n), j = (int)(idx % n);
-        const int p = pp[pr], q = qq[pr];
-        if (p == q) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[(int64_t)p * n + j], aq = A[(int64_t)q * n + j];
-        A[(int64_t)p * n + j] = c * ap - s * aq;
-        A[(int64_t)q * n + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      for (int64_t idx = tid; idx < (int64_t)(K / 2) * n; idx += 256) {
-        const int pr = (int)(idx / n), i = (int)(idx % n);
-        const int p = pp[pr], q = qq[pr];
-        if (p == q) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[(int64_t)i * n + p], aq = A[(int64_t)i * n + q];
-        A[(int64_t)i * n + p] = c * ap - s * aq;
-        A[(int64_t)i * n + q] = s * ap + c * aq;
-        const double vp = V[(int64_t)i * n + p], vq = V[(int64_t)i * n + q];
-        V[(int64_t)i * n + p] = c * vp - s * vq;
-        V[(int64_t)i * n + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-  }
+__device__ __forceinline__ void pair_of(int K, int pr, int r, int& I, int& J) {
+  const int a = pr == 0 ? 0 : 1 + ((pr - 1 + r) % (K - 1));
+  const int b = 1 + ((K - 1 - pr - 1 + r) % (K - 1));
+  I = a < b ? a : b;
+  J = a < b ? b : a;
 }
 
-hipError_t launch_sym_jacobi(const EigJob* jobs, int n_jobs, double* A, double* V, hipStream_t s) {
+// rows: the pair's row indices (nr of them); X: rows of length len at base
+// with row stride len; out = Q^T X (in place)
+__device__ void rotate_rows(double* base, int64_t len, const int* rows, int nr, const double (*Q)[R2 + 1],
+                            double (*buf)[CH + 1]) {
+  const int tid = threadIdx.x;
+  for (int64_t c0 = 0; c0 < len; c0 += CH) {
+    const int w = (int)min<int64_t>(CH, len - c0);
+    for (int e = tid; e < nr * CH; e += 256) {
+      const int i = e / CH, j = e % CH;
+      buf[i][j] = j < w ? base[(int64_t)rows[i] * len + c0 + j] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * CH; e += 256) {
+      const int i = e / CH, j = e % CH;
+      if (j >= w) continue;
+      double v = 0.0;
+      for (int k = 0; k < nr; ++k) v += Q[k][i] * buf[k][j];
+      base[(int64_t)rows[i] * len + c0 + j] = v;
+    }
+    __syncthreads();
+  }
+}
+}  // namespace bjk
+
+__global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__ jobs, double* __restrict__ Ball,
+                                                       double* __restrict__ WTall, unsigned long long* off_max, int r,
+                                                       double tol) {
+  using namespace bjk;
+  __shared__ double G[R2][R2 + 1];
+  __shared__ double Q[R2][R2 + 1];
+  __shared__ double buf[R2][CH + 1];
+  __shared__ double cs[R2 / 2], sn[R2 / 2], dpp[R2 / 2], dqq[R2 / 2];
+  __shared__ int pp[R2 / 2], qq[R2 / 2];
+  __shared__ int rows[R2], rank_of[R2];
+  __shared__ double red[256];
+  __shared__ int flag;
+  const BjJob jb = jobs[blockIdx.x];
+  if (r >= jb.K - 1) return;
+  int I, J;
+  pair_of(jb.K, jb.pr, r, I, J);
+  const int m = jb.m;
+  const int nb = (m + kBjRows - 1) / kBjRows;
+  const int tid = threadIdx.x;
+  // paired with the padding block of an odd block count (or the only
+  // block): block I alone, whose own rows still need orthogonalizing
+  const int nI = min(kBjRows, m - kBjRows * I), nJ = J < nb ? min(kBjRows, m - kBjRows * J) : 0;
+  const int nr = nI + nJ;
+  if (tid < nr) rows[tid] = tid < nI ? kBjRows * I + tid : kBjRows * J + (tid - nI);
+  __syncthreads();
+  double* B = Ball + jb.b_off;
+  double* WT = WTall + jb.w_off;
+  // Gram matrix of the pair's rows of B
+  double g[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = 0; c0 < jb.c; c0 += CH) {
+    const int w = (int)min<int64_t>(CH, jb.c - c0);
+    for (int e = tid; e < nr * CH; e += 256) {
+      const int i = e / CH, j = e % CH;
+      buf[i][j] = j < w ? B[(int64_t)rows[i] * jb.c + c0 + j] : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      if (e >= nr * nr) break;
+      const int i = e / nr, j = e % nr;
+      double v = 0.0;
+      for (int k = 0; k < w; ++k) v += buf[i][k] * buf[j][k];
+      g[t] += v;
+    }
+    __syncthreads();
+  }
+  for (int t = 0; t < 4; ++t) {
+    const int e = tid + 256 * t;
+    if (e < nr * nr) G[e / nr][e % nr] = g[t];
+  }
+  for (int e = tid; e < R2 * R2; e += 256) Q[e / R2][e % R2] = (e / R2 == e % R2) ? 1.0 : 0.0;
+  __syncthreads();
+  // largest relative off-diagonal entry
+  double off = 0.0;
+  for (int e = tid; e < nr * nr; e += 256) {
+    const int i = e / nr, j = e % nr;
+    if (i == j) continue;
+    if (G[i][i] > jb.small2 && G[j][j] > jb.small2) off = fmax(off, fabs(G[i][j]) / sqrt(G[i][i] * G[j][j]));
+  }
+  red[tid] = off;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] = fmax(red[tid], red[tid + st]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    atomicMax(off_max + jb.sector, (unsigned long long)__double_as_longlong(red[0]));
+    flag = red[0] > tol * sqrt((double)jb.c) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!flag) return;
+  // eigenvectors of G: cyclic Jacobi, round-robin pairs; a pair is rotated
+  // while |G_pq| > 1e-15 sqrt(G_pp G_qq) (relative to the pair's own scale,
+  // which keeps rows of very different norms accurate) and neither row is
+  // negligible (G_pp, G_qq above small2), until a sweep rotates nothing.
+  // The rotated 2 x 2 block is set from the closed form (G_pp - t G_pq,
+  // G_qq + t G_pq, 0), so that no rounding residue of the large diagonal
+  // entry stays in G_pq.
+  const int P = (nr + 1) & ~1;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int rr = 0; rr < P - 1; ++rr) {
+      if (tid < P / 2) {
+        const int a = tid == 0 ? 0 : 1 + ((tid - 1 + rr) % (P - 1));
+        const int b = 1 + ((P - 1 - tid - 1 + rr) % (P - 1));
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sv = 0.0;
+        if (q < nr && fmin(G[p][p], G[q][q]) > jb.small2 && fabs(G[p][q]) > 1e-15 * sqrt(G[p][p] * G[q][q])) {
+          const double th = (G[q][q] - G[p][p]) / (2.0 * G[p][q]);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sv = t * c;
+          dpp[tid] = G[p][p] - t * G[p][q];
+          dqq[tid] = G[q][q] + t * G[p][q];
+          flag = 1;
+        }
+        cs[tid] = c;
+        sn[tid] = sv;
+        pp[tid] = p;
+        qq[tid] = (q < nr && sv != 0.0) ? q : p;
+      }
+      __syncthreads();
+      for (int e = tid; e < (P / 2) * nr; e += 256) {  // rows of G
+        const int k = e / nr, j = e % nr;
+        const int p = pp[k], q = qq[k];
+        if (p == q) continue;
+        const double gp = G[p][j], gq = G[q][j];
+        G[p][j] = cs[k] * gp - sn[k] * gq;
+        G[q][j] = sn[k] * gp + cs[k] * gq;
+      }
+      __syncthreads();
+      for (int e = tid; e < (P / 2) * nr; e += 256) {  // columns of G and of Q
+        const int k = e / nr, i = e % nr;
+        const int p = pp[k], q = qq[k];
+        if (p == q) continue;
+        const double gp = G[i][p], gq = G[i][q];
+        G[i][p] = cs[k] * gp - sn[k] * gq;
+        G[i][q] = sn[k] * gp + cs[k] * gq;
+        const double vp = Q[i][p], vq = Q[i][q];
+        Q[i][p] = cs[k] * vp - sn[k] * vq;
+        Q[i][q] = sn[k] * vp + cs[k] * vq;
+      }
+      __syncthreads();
+      if (tid < P / 2) {
+        const int p = pp[tid], q = qq[tid];
+        if (p != q) {
+          G[p][p] = dpp[tid];
+          G[q][q] = dqq[tid];
+          G[p][q] = 0.0;
+          G[q][p] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    if (!flag) break;
+    __syncthreads();
+  }
+  // eigenvectors in descending order of their eigenvalue: the pair's
+  // larger rows move to its lower block, which shortens the sweeps much
+  // like the row sorting of de Rijk's one-sided Jacobi
+  if (tid < nr) {
+    const double d = G[tid][tid];
+    int rk = 0;
+    for (int j = 0; j < nr; ++j) rk += (G[j][j] > d || (G[j][j] == d && j < tid)) ? 1 : 0;
+    rank_of[tid] = rk;
+  }
+  __syncthreads();
+  for (int e = tid; e < nr * nr; e += 256) {
+    const int k = e / nr, i = e % nr;
+    G[k][rank_of[i]] = Q[k][i];
+  }
+  __syncthreads();
+  rotate_rows(B, jb.c, rows, nr, G, buf);
+  rotate_rows(WT, m, rows, nr, G, buf);
+}
+
+hipError_t launch_bj_round(const BjJob* jobs, int n_jobs, double* B, double* WT, unsigned long long* off_max, int r,
+                           double tol, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sym_jacobi_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, A, V);
+  hipLaunchKernelGGL(bj_round_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, B, WT, off_max, r, tol);
   return hipGetLastError();
 }
 
-// Columns of the new isometry: out[r * ncol + j] = sign_j * V[r * n + col_j]
-// with sign_j making the largest-magnitude entry of the column positive.
-__global__ __launch_bounds__(256) void gather_columns_kernel(const GatherJob* __restrict__ jobs,
-                                                            const double* __restrict__ V_all, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void copy_blocks_kernel(const CopyJob* __restrict__ jobs, const double* __restrict__ src,
+                                                          double* __restrict__ dst) {
+  const CopyJob j = jobs[blockIdx.x];
+  for (int e = threadIdx.x; e < j.rows * j.cols; e += 256)
+    dst[j.dst + (int64_t)(e / j.cols) * j.ld + e % j.cols] = src[j.src + e];
+}
+hipError_t launch_copy_blocks(const CopyJob* jobs, int n_jobs, const double* src, double* dst, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_blocks_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, src, dst);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void identity_kernel(const int64_t* __restrict__ woff, const int32_t* __restrict__ m,
+                                                       double* __restrict__ WT) {
+  const int q = blockIdx.x;
+  const int n = m[q];
+  double* W = WT + woff[q];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) W[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+hipError_t launch_identity(const int64_t* woff, const int32_t* m, int n_sect, double* WT, hipStream_t s) {
+  if (n_sect <= 0) return hipSuccess;
+  hipLaunchKernelGGL(identity_kernel, dim3(n_sect), dim3(256), 0, s, woff, m, WT);
+  return hipGetLastError();
+}
+
+// one work-group per sector, one wave per row at a time (fixed-order sums)
+__global__ __launch_bounds__(256) void row_norms_kernel(const int64_t* __restrict__ boff, const int32_t* __restrict__ m,
+                                                        const int32_t* __restrict__ c, const int64_t* __restrict__ soff,
+                                                        const double* __restrict__ B, double* __restrict__ sig) {
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < m[q]; i += 4) {
+    const double* row = B + boff[q] + (int64_t)i * c[q];
+    double v = 0.0;
+    for (int j = lane; j < c[q]; j += 64) v += row[j] * row[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (lane == 0) sig[soff[q] + i] = sqrt(v);
+  }
+}
+hipError_t launch_row_norms(const int64_t* boff, const int32_t* m, const int32_t* c, const int64_t* soff, int n_sect,
+                            const double* B, double* sig, hipStream_t s) {
+  if (n_sect <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_norms_kernel, dim3(n_sect), dim3(256), 0, s, boff, m, c, soff, B, sig);
+  return hipGetLastError();
+}
+
+// kept left singular vectors (rows of W^T) as isometry columns
+__global__ __launch_bounds__(256) void gather_rows_kernel(const GatherJob* __restrict__ jobs, const double* __restrict__ WT,
+                                                          double* __restrict__ out) {
   __shared__ double bv[256];
   __shared__ int bi[256];
   const GatherJob J = jobs[blockIdx.x];
-  const double* V = V_all + J.v_off;
   const int n = J.n;
   for (int j = 0; j < J.ncol; ++j) {
-    const int col = J.cols[j];
+    const double* u = WT + J.v_off + (int64_t)J.cols[j] * n;
     double best = -1.0;
     int idx = 0;
     for (int r = threadIdx.x; r < n; r += 256) {
-      const double a = fabs(V[(int64_t)r * n + col]);
+      const double a = fabs(u[r]);
       if (a > best) { best = a; idx = r; }
     }
     bv[threadIdx.x] = best;
@@ -1495,16 +1646,14 @@ __global__ __launch_bounds__(256) void gather_columns_kernel(const GatherJob* __
       }
       __syncthreads();
     }
-    const double sg = V[(int64_t)bi[0] * n + col] < 0 ? -1.0 : 1.0;
+    const double sg = u[bi[0]] < 0 ? -1.0 : 1.0;
     __syncthreads();
-    for (int r = threadIdx.x; r < n; r += 256) out[J.out_off + (int64_t)r * J.ncol + j] = sg * V[(int64_t)r * n + col];
-    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += 256) out[J.out_off + (int64_t)r * J.ncol + j] = sg * u[r];
   }
 }
-
-hipError_t launch_gather_columns(const GatherJob* jobs, int n_jobs, const double* V, double* out, hipStream_t s) {
+hipError_t launch_gather_rows(const GatherJob* jobs, int n_jobs, const double* WT, double* out, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_columns_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, V, out);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(n_jobs), dim3(256), 0, s, jobs, WT, out);
   return hipGetLastError();
 }
 

@@ -370,27 +370,63 @@ hipError_t launch_gemm_f64(int64_t m, int64_t n, int64_t k, const double* A, con
   });
 }
 
-hipError_t launch_sym_jacobi(const EigJob* jobs, int n_jobs, double* A, double* V, hipStream_t) {
+hipError_t launch_bj_round(const BjJob* jobs, int n_jobs, double* B, double* WT, unsigned long long* off_max, int r,
+                           double, hipStream_t) {
   return hc::run([=]() {
-    if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(EigJob), "eigen jobs")) return;
+    if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(BjJob), "block-Jacobi jobs")) return;
     for (int i = 0; i < n_jobs; ++i) {
-      if (jobs[i].n > kMaxEig) hc::violation("eigen job %d: n = %d above %d", i, jobs[i].n, kMaxEig);
-      hc::check_range(A + jobs[i].off, (size_t)jobs[i].n * jobs[i].n * 8, "eigen matrix");
-      hc::check_range(V + jobs[i].off, (size_t)jobs[i].n * jobs[i].n * 8, "eigenvectors");
+      const BjJob j = jobs[i];
+      if (j.K % 2 || j.pr < 0 || j.pr >= j.K / 2) hc::violation("block-Jacobi job %d: pair %d of %d blocks", i, j.pr, j.K);
+      if ((j.K - 1) * kBjRows >= j.m + kBjRows * 2) hc::violation("block-Jacobi job %d: %d blocks for %d rows", i, j.K, j.m);
+      hc::check_range(B + j.b_off, (size_t)j.m * j.c * 8, "block-Jacobi rows of B");
+      hc::check_range(WT + j.w_off, (size_t)j.m * j.m * 8, "block-Jacobi rows of W^T");
+      hc::check_range(off_max + j.sector, 8, "block-Jacobi convergence slot");
+    }
+    (void)r;
+  });
+}
+
+hipError_t launch_copy_blocks(const CopyJob* jobs, int n_jobs, const double* src, double* dst, hipStream_t) {
+  return hc::run([=]() {
+    if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(CopyJob), "copy jobs")) return;
+    for (int i = 0; i < n_jobs; ++i) {
+      const CopyJob j = jobs[i];
+      if (j.cols > j.ld) hc::violation("copy job %d: %d columns into stride %d", i, j.cols, j.ld);
+      hc::check_range(src + j.src, (size_t)j.rows * j.cols * 8, "copy source block");
+      if (j.rows > 0) hc::check_range(dst + j.dst, (size_t)((j.rows - 1) * (int64_t)j.ld + j.cols) * 8, "copy destination block");
     }
   });
 }
 
-hipError_t launch_gather_columns(const GatherJob* jobs, int n_jobs, const double* V, double* out, hipStream_t) {
+hipError_t launch_identity(const int64_t* woff, const int32_t* m, int n_sect, double* WT, hipStream_t) {
+  return hc::run([=]() {
+    if (!hc::check_range(woff, (size_t)n_sect * 8, "identity offsets") || !hc::check_range(m, (size_t)n_sect * 4, "identity sizes"))
+      return;
+    for (int q = 0; q < n_sect; ++q) hc::check_range(WT + woff[q], (size_t)m[q] * m[q] * 8, "identity matrix");
+  });
+}
+
+hipError_t launch_row_norms(const int64_t* boff, const int32_t* m, const int32_t* c, const int64_t* soff, int n_sect,
+                            const double* B, double* sig, hipStream_t) {
+  return hc::run([=]() {
+    for (int q = 0; q < n_sect; ++q) {
+      hc::check_range(B + boff[q], (size_t)m[q] * c[q] * 8, "row-norm rows");
+      hc::check_range(sig + soff[q], (size_t)m[q] * 8, "row norms");
+    }
+  });
+}
+
+hipError_t launch_gather_rows(const GatherJob* jobs, int n_jobs, const double* WT, double* out, hipStream_t) {
   return hc::run([=]() {
     if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(GatherJob), "gather jobs")) return;
     for (int i = 0; i < n_jobs; ++i) {
       const GatherJob g = jobs[i];
-      if (!hc::check_range(g.cols, (size_t)g.ncol * 4, "gather columns")) continue;
-      hc::check_range(V + g.v_off, (size_t)g.n * g.n * 8, "gather source");
+      if (!hc::check_range(g.cols, (size_t)g.ncol * 4, "gather rows")) continue;
+      for (int c = 0; c < g.ncol; ++c) {
+        if (g.cols[c] < 0 || g.cols[c] >= g.n) hc::violation("gather job %d: row %d of %d", i, g.cols[c], g.n);
+        else hc::check_range(WT + g.v_off + (int64_t)g.cols[c] * g.n, (size_t)g.n * 8, "gathered row");
+      }
       hc::check_range(out + g.out_off, (size_t)g.n * g.ncol * 8, "gather destination");
-      for (int c = 0; c < g.ncol; ++c)
-        if (g.cols[c] < 0 || g.cols[c] >= g.n) hc::violation("gather job %d: column %d of %d", i, g.cols[c], g.n);
     }
   });
 }

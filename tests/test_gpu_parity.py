@@ -464,6 +464,41 @@ def test_truncation_matches_oracle(heff, ctx, N, D, keep, planted):
 
 
 
+def test_truncation_graded_spectrum(heff, ctx):
+    # singular values spread over ten decades inside every enlarged sector:
+    # the small ones must keep their relative accuracy (the SVD works on M
+    # itself; the eigenvalues of M M^T would lose every small singular value
+    # below about 1e-8 of the largest)
+    from oracle import svd
+    p = synth.make_problem(10, 32, 7)
+    rng = np.random.default_rng(12)
+    psi = np.zeros(synth.psi_size(p))
+    planted = []
+    blocks = {(b[0], b[1], b[2]): b for b in synth.psi_blocks(p)}
+    for qp, (M, rows, cols) in svd.sector_matrices(p, psi).items():
+        r = min(M.shape)
+        U0, _ = np.linalg.qr(rng.standard_normal((M.shape[0], r)))
+        V0, _ = np.linalg.qr(rng.standard_normal((M.shape[1], r)))
+        sig = 10.0 ** -np.linspace(0.0, 10.0, r) if r > 1 else np.ones(1)
+        planted += list(sig)
+        Mq = U0 @ np.diag(sig) @ V0.T
+        r0 = 0
+        for (s_, qa, da) in rows:
+            c0 = 0
+            for (s1, qb, db) in cols:
+                b = blocks[(qa, s_, s1)]
+                psi[b[6]: b[6] + da * db] = Mq[r0:r0 + da, c0:c0 + db].reshape(-1)
+                c0 += db
+            r0 += da
+    planted = np.sort(np.array(planted))[::-1]
+    B = heff.Blocks(ctx, p)
+    out = B.truncate(_dev(psi), len(planted))
+    got = out["sing"]
+    err = np.abs(got - planted)
+    print("max abs err %.2e, max rel err %.2e" % (err.max(), (err / planted).max()))
+    assert np.all(err <= 1e-14 + 1e-6 * planted)
+
+
 def test_truncation_full_size_n40_d4096(heff, ctx):
     # the truncation step at the timed configuration (N=40, D=4096, seed 3):
     # 201 enlarged sectors up to 488 wide, keep D = 4096 states
