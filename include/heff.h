@@ -396,6 +396,103 @@ int heff_davidson_step(heff_ctx* ctx, heff_dav* d, int prec, double* theta, doub
 int heff_dav_ritz(heff_ctx* ctx, heff_dav* d, double* psi);
 int heff_dav_free(heff_dav* d);
 
+/* SU(2) spin-adapted product (Sec. II.C, Eq. Hamilton_act_su2).
+ *
+ * States are grouped into spin multiplets and operators into irreducible
+ * tensor operators stored by their reduced matrix elements, with the
+ * Wigner-Eckart convention <j' m'|T^k_q|j m> = <j m; k q|j' m'> <j'||T^k||j>
+ * (Condon-Shortley Clebsch-Gordan coefficients).  The two-site space is
+ * coupled hierarchically: left block x site k -> gamma, site k+1 x right
+ * block -> delta, gamma x delta -> the total spin.  Each Hamiltonian term
+ * is the scalar [[O_L x O_k]^S x [O_k1 x O_R]^S]^0 of a left-block operator,
+ * two site operators and a right-block operator; it becomes one task per
+ * (input block, output block) with the scalar prefactor
+ * coef * sign * <k'||O_k||k> <k1'||O_k1||k1> * F_L * F_R * F_T, each F a
+ * rescaled Wigner 9j symbol, sqrt((2a'+1)(2b'+1)(2c+1)(2k_c+1)) *
+ * {a b c; k_a k_b k_c; a' b' c'}, taken from a lookup table filled on first
+ * use.  sign is the Jordan-Wigner sign (-1)^(|O_k| n_l + |O_k1| (n_l + n_k)
+ * + |O_R| (n_l + n_k + n_k1)) of the input particle numbers (subsystem
+ * order L, k, k+1, R; |O| = 1 for an odd change of the particle number).
+ * The tasks run on the same matrix-core kernels as the U(1) product.
+ *
+ * All spins are doubled integers (two_s = 2 S).  Site multiplets of one
+ * spatial orbital: 0 empty (n 0, S 0), 1 doublet (n 1, S 1/2), 2 doubly
+ * occupied singlet (n 2, S 0).  Site operators by code: 0 identity, 1
+ * creation tensor (a+_{+1/2} = c+_up, a+_{-1/2} = c+_down), 2 annihilation
+ * tensor (a~_{+1/2} = c_down, a~_{-1/2} = -c_up), 3 number, 4 spin vector
+ * (T_{+1} = -S+/sqrt2, T_0 = S_z, T_{-1} = S-/sqrt2), 5 pair creation
+ * c+_up c+_down, 6 pair annihilation c_down c_up; the doubly occupied state
+ * is c+_up c+_down |0>.
+ *
+ * heff_su2_block: one block's multiplet sectors (n[i], two_s[i], dim[i]
+ * multiplets, 1 <= dim <= 256, two_s of the parity of n, no repeated
+ * (n, two_s)) and its operators (two_k[j] doubled rank, dn[j] change of
+ * the particle number, two_k of the parity of dn); n_blk reduced blocks
+ * (op blk_op[b], sectors blk_in[b] -> blk_out[b] with n_out = n_in + dn and
+ * two_s_out in two_s_in x two_k), each a row-major dim_out x dim_in matrix
+ * at data + blk_off[b] (host, copied at creation).  Missing blocks are
+ * zero.  heff_su2_problem: both blocks, n_terms terms (term_l / term_r: an
+ * operator index or -1 for the identity of the block; term_site_k /
+ * term_site_k1: site operator codes; term_two_s: doubled rank S of the
+ * coupled left and right parts; term_coef), the total particle number and
+ * doubled total spin.  Terms must conserve the particle number and satisfy
+ * the triangle rules of their couplings.
+ *
+ * Reduced two-site vector: row-major blocks dim_l x dim_r for every key
+ * (il, mk, two_s_gamma, mk1, ir, two_s_delta) -- left sector, site-k
+ * multiplet, doubled spin of left x site k, site-(k+1) multiplet, right
+ * sector, doubled spin of site k+1 x right -- with n_l + n_k + n_k1 + n_r =
+ * n_tot and two_s_tot in gamma x delta, in lexicographic key order,
+ * concatenated.  heff_su2_layout() returns it: desc holds 8 int32 per block
+ * (the key, rows, cols), off the element offsets (library-owned).
+ *
+ * heff_su2_create(): validates the problem on the host (HEFF_EINVAL with a
+ * message on any violation, HEFF_ESECTOR if the target space is empty),
+ * builds the task table and uploads the operator data; prec_mask as in
+ * heff_build_blocks (FP64 always; bits HEFF_FP32 / HEFF_BF16X3 add FP32
+ * operand copies).  heff_su2_apply(): out = H psi on the context's stream
+ * (device vectors of n_elem elements of the precision's type, no alias).
+ * heff_su2_stats(): tasks, algorithmic flops per product (the U(1) count
+ * per task) and the number of magnetic-resolved amplitudes the reduced
+ * vector stands for at M = S_tot (sum over blocks of rows x cols x the
+ * dimension of their M = S_tot subspace, for comparison with a U(1)
+ * vector).  heff_su2_factor(): F(a, b, c; k_a, k_b, k_c; a', b', c') for
+ * doubled spins two_j[9] in that order (host only, no context). */
+typedef struct heff_su2 heff_su2;
+typedef struct {
+  int32_t n_sect;
+  const int32_t* n;
+  const int32_t* two_s;
+  const int32_t* dim;
+  int32_t n_ops;
+  const int32_t* two_k;
+  const int32_t* dn;
+  int64_t n_blk;
+  const int32_t* blk_op;
+  const int32_t* blk_out;
+  const int32_t* blk_in;
+  const int64_t* blk_off;
+  const double* data;
+  int64_t data_len;
+} heff_su2_block;
+typedef struct {
+  heff_su2_block left, right;
+  int32_t n_terms;
+  const int32_t* term_l;
+  const int32_t* term_site_k;
+  const int32_t* term_site_k1;
+  const int32_t* term_r;
+  const int32_t* term_two_s;
+  const double* term_coef;
+  int32_t n_tot, two_s_tot;
+} heff_su2_problem;
+int heff_su2_create(heff_ctx* ctx, const heff_su2_problem* p, uint32_t prec_mask, heff_su2** out);
+int heff_su2_layout(const heff_su2* h, int64_t* n_elem, int32_t* n_blk, const int32_t** desc, const int64_t** off);
+int heff_su2_stats(const heff_su2* h, int64_t* n_tasks, double* flops, double* n_resolved);
+int heff_su2_apply(heff_ctx* ctx, const heff_su2* h, int prec, const void* psi, void* out);
+int heff_su2_free(heff_su2* h);
+int heff_su2_factor(const int32_t two_j[9], double* F);
+
 #ifdef __cplusplus
 }
 #endif

@@ -431,11 +431,15 @@ def _block_op_or_id(blk, j, o, i):
     return blk.ops[j][2].get((o, i))
 
 
-def apply_tasks(p, psi):
-    """Sum over terms and input blocks of F_tau f L_blk psi_blk R_blk^T."""
+def apply_tasks(p, psi, only=None):
+    """Sum over terms and input blocks of F_tau f L_blk psi_blk R_blk^T
+    (only: if given, the set of output block keys to compute; the others
+    stay zero)."""
     red = site_reduced()
     blocks = S.psi_blocks(p)
     where = {key: (off, r, c) for key, off, r, c in blocks}
+    only_l = None if only is None else {k[0] for k in only}
+    only_r = None if only is None else {k[4] for k in only}
     y = np.zeros_like(psi)
     for (l, sk, sk1, r, tc, coef) in p.terms:
         tA = 0 if l < 0 else p.L.ops[l][0]
@@ -451,6 +455,8 @@ def apply_tasks(p, psi):
             nk, nk1 = S.SITE_MULT[mk][0], S.SITE_MULT[mk1][0]
             sign = (-1.0) ** ((dB % 2) * nl + (dC % 2) * (nl + nk) + oD * (nl + nk + nk1))
             for sl2 in range(len(p.L.sectors)):
+                if only_l is not None and sl2 not in only_l:
+                    continue
                 Lb = _block_op_or_id(p.L, l, sl2, sl)
                 if Lb is None:
                     continue
@@ -463,13 +469,15 @@ def apply_tasks(p, psi):
                         if rc is None:
                             continue
                         for sr2 in range(len(p.R.sectors)):
+                            if only_r is not None and sr2 not in only_r:
+                                continue
                             Rb = _block_op_or_id(p.R, r, sr2, sr)
                             if Rb is None:
                                 continue
                             for tsg2 in S.couple(p.L.sectors[sl2][1], S.SITE_MULT[mk2][1]):
                                 for tsd2 in S.couple(S.SITE_MULT[mk12][1], p.R.sectors[sr2][1]):
                                     k2 = (sl2, mk2, tsg2, mk12, sr2, tsd2)
-                                    if k2 not in where:
+                                    if k2 not in where or (only is not None and k2 not in only):
                                         continue
                                     fl = factor_fig(p.L.sectors[sl][1], S.SITE_MULT[mk][1], tsg, tA, tB, tc,
                                                     p.L.sectors[sl2][1], S.SITE_MULT[mk2][1], tsg2)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libheff.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("heff_host.hip", "heff_kernels.hip", "heff_davidson.hip", "heff_noalloc.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("heff_host.hip", "heff_kernels.hip", "heff_davidson.hip", "heff_noalloc.hip", "heff_su2.hip")]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

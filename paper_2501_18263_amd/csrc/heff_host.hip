@@ -17,37 +17,9 @@
 // right block keeps a_r, a_s a_r, a+_q a_s, S_x (x outside R) and H_R.
 // A product l (x) m (x) r acting on |l>|mid>|r> carries
 // (-1)^(|m| n(l) + |r| (n(l) + n(mid))) for the input particle numbers.
-#include "heff_internal.h"
-#include "../../include/heff.h"
-
-#include <algorithm>
-#include <array>
-#include <atomic>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <functional>
-#include <map>
-#include <memory>
-#include <set>
-#include <stdexcept>
-#include <string>
-#include <thread>
-#include <vector>
+#include "heff_host_common.h"
 
 namespace heff {
-
-struct Error : std::runtime_error {
-  int code;
-  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
-#define HCHECK(x)                                                                          \
-  do {                                                                                     \
-    hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess)                                                                  \
-      throw Error(HEFF_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));              \
-  } while (0)
 
 // ------------------------------------------------------------------ device memory
 thread_local Alloc tl_alloc;
@@ -69,44 +41,6 @@ void dev_free(void* p, const Alloc& a) {
   if (!p) return;
   if (a.fa) a.ff(p, a.user);
   else (void)hipFree(p);
-}
-
-// C-ABI calls on a context allocate through its provider
-struct AllocScope {
-  Alloc saved;
-  explicit AllocScope(const heff_ctx* c) : saved(tl_alloc) { tl_alloc = c ? c->alloc : Alloc{}; }
-  ~AllocScope() { tl_alloc = saved; }
-};
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  Alloc al;  // provider p came from
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { release(); }
-  void alloc(size_t n) {
-    release();
-    if (n == 0) n = 256;
-    al = tl_alloc;
-    p = dev_alloc(n, al);
-    if (!p) throw Error(HEFF_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
-    bytes = n;
-  }
-  void release() {
-    dev_free(p, al);
-    p = nullptr;
-    bytes = 0;
-  }
-  template <typename T>
-  T* as() const { return reinterpret_cast<T*>(p); }
-};
-
-template <typename T>
-static void upload(DevBuf& d, const std::vector<T>& v, hipStream_t s) {
-  d.alloc(v.size() * sizeof(T));
-  if (!v.empty()) HCHECK(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
 // ------------------------------------------------------------------ sectors
@@ -499,7 +433,7 @@ static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
 
 // Largest dimension a tile's kernels hold in registers: the output width e
 // and the middle dimension c of its tasks (T = op(L) op(X) has c columns).
-static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
+int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
   int d = t.e;
   for (int k = t.t0; k < t.t1; ++k) d = std::max<int>(d, tasks[k].c);
   return d;
@@ -517,7 +451,7 @@ static int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
 // starts its longest items first (a longest-processing-time order; items of
 // one tile have the same estimate and stay adjacent, so they run side by
 // side).  Unused positions hold row0 = -1 (the kernels skip them).
-static double task_flops(const Task& t);
+double task_flops(const Task& t);
 
 // Estimated run time of one 64-row work item of a tile, in units of one
 // 16x16x4 matrix instruction per wave: every pipeline step costs a fixed
@@ -540,9 +474,8 @@ static double item_cost(const Tile& tile, const std::vector<Task>& tasks) {
   return cost;
 }
 
-static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks,
-                       const std::vector<int>& order, std::vector<Work> (&lists)[kNumVariants],
-                       const std::vector<int>* key = nullptr) {
+void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks, const std::vector<int>& order,
+                std::vector<Work> (&lists)[kNumVariants], const std::vector<int>* key) {
   constexpr int kXcd = 8;
   std::vector<double> icost(tiles.size(), 0.0);
   for (size_t t = 0; t < tiles.size(); ++t) icost[t] = item_cost(tiles[t], tasks);
@@ -597,21 +530,9 @@ static void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& 
   }
 }
 
-struct DevWorkSet {
-  DevBuf buf[kNumVariants];
-  WorkSet ws{};
-  void upload_lists(std::vector<Work> (&lists)[kNumVariants], hipStream_t s) {
-    for (int v = 0; v < kNumVariants; ++v) {
-      upload(buf[v], lists[v], s);
-      ws.w[v] = buf[v].as<Work>();
-      ws.n[v] = (int64_t)lists[v].size();
-    }
-  }
-};
-
 // Readable element counts of the FP64 operand buffers (the ring kernel's
 // 16-byte loads stay inside them).
-static int64_t elems64(const DevBuf& d) { return (int64_t)(d.bytes / sizeof(double)); }
+int64_t elems64(const DevBuf& d) { return (int64_t)(d.bytes / sizeof(double)); }
 static void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, const DevBuf& x0, const DevBuf& x1,
                        const DevBuf& r0, const DevBuf& r1) {
   b.lim[0] = elems64(l0);
@@ -621,7 +542,7 @@ static void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, con
   b.lim[4] = elems64(r0);
   b.lim[5] = elems64(r1);
 }
-static void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, int64_t x, const DevBuf& r0,
+void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, int64_t x, const DevBuf& r0,
                        const DevBuf& r1) {
   b.lim[0] = elems64(l0);
   b.lim[1] = elems64(l1);
@@ -1267,7 +1188,7 @@ static void build_psi_layout(heff_blocks& B) {
   if (B.blk_off.empty()) throw Error(HEFF_ESECTOR, "no two-site block in the target sector");
 }
 
-static double task_flops(const Task& t) {
+double task_flops(const Task& t) {
   double a = t.a, b = t.b, c = t.c, e = t.e;
   bool idl = t.flags & T_IDL, idr = t.flags & T_IDR;
   if (idl && idr) return 2.0 * a * e;
@@ -1565,25 +1486,6 @@ extern "C" int heff_validate_problem(const heff_problem* prob, char* msg, int32_
   return HEFF_OK;
 }
 
-#define ABI_BEGIN                    \
-  heff::AllocScope alloc_scope_(ctx); \
-  try {
-#define ABI_END(ctx)                                                \
-  }                                                                 \
-  catch (const Error& e) {                                          \
-    if (ctx) (ctx)->err = e.what();                                 \
-    return e.code;                                                  \
-  }                                                                 \
-  catch (const std::bad_alloc&) {                                   \
-    if (ctx) (ctx)->err = "host allocation failed";                 \
-    return HEFF_ENOMEM;                                             \
-  }                                                                 \
-  catch (const std::exception& e) {                                 \
-    if (ctx) (ctx)->err = e.what();                                 \
-    return HEFF_EINVAL;                                             \
-  }                                                                 \
-  return HEFF_OK;
-
 namespace heff {
 // Streams of the product's kernel variants, forked from the context stream
 // (so the variants run concurrently: the small-block variants are bound by
@@ -1598,7 +1500,7 @@ static hipError_t make_variant_streams(heff_ctx* c) {
   }
   return e;
 }
-static void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
+void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
   HCHECK(make_variant_streams(c));
   HCHECK(hipEventRecord(c->fork, c->stream));
   for (int v = 0; v < kNumVariants; ++v) {
@@ -1606,7 +1508,7 @@ static void fork_variants(heff_ctx* c, hipStream_t out[kNumVariants]) {
     out[v] = c->vs[v];
   }
 }
-static void join_variants(heff_ctx* c) {
+void join_variants(heff_ctx* c) {
   for (int v = 0; v < kNumVariants; ++v) {
     HCHECK(hipEventRecord(c->join[v], c->vs[v]));
     HCHECK(hipStreamWaitEvent(c->stream, c->join[v], 0));
@@ -1820,20 +1722,14 @@ extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, in
 bool heff::blocks_sharded(const heff_blocks* b) { return b && b->shard_nranks > 1; }
 int64_t heff::blocks_n_elem(const heff_blocks* b) { return b ? b->n_elem : 0; }
 
-extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
-  if (!ctx) return HEFF_EINVAL;
-  ABI_BEGIN
-  if (!b || !psi || !out) throw Error(HEFF_EINVAL, "null argument");
-  if (psi == out) throw Error(HEFF_EINVAL, "psi and out alias");
-  HCHECK(hipSetDevice(ctx->device));
-  hipStream_t s = ctx->stream;
-  const Tile* tl = b->d_tiles.as<Tile>();
-  const Task* tk = b->d_tasks.as<Task>();
+namespace heff {
+void run_product(heff_ctx* ctx, const Tile* tl, const Task* tk, const WorkSet& ws, int prec, uint32_t prec_mask,
+                 Bases<double> b64, Bases<float> b32, const void* psi, void* out) {
   hipEvent_t evbuf[kNumVariants][2] = {};
   hipEvent_t(*ev)[2] = nullptr;
   if (ctx->timing) {
     for (int v = 0; v < kNumVariants; ++v) {
-      if (b->mwork.ws.n[v] <= 0) continue;
+      if (ws.n[v] <= 0) continue;
       HCHECK(hipEventCreate(&evbuf[v][0]));
       HCHECK(hipEventCreate(&evbuf[v][1]));
       ctx->ev_start[v].push_back(evbuf[v][0]);
@@ -1841,53 +1737,51 @@ extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const v
     }
     ev = evbuf;
   }
+  hipStream_t vs[kNumVariants];
   if (prec == HEFF_FP64) {
-    Bases<double> bs{};
-    bs.L[0] = b->L->store.dev.as<double>();
-    bs.L[1] = b->Ltmp.tmp.dev.as<double>();
-    bs.R[0] = b->R->store.dev.as<double>();
-    bs.R[1] = b->Rtmp.tmp.dev.as<double>();
-    bs.X[0] = bs.X[1] = static_cast<const double*>(psi);
-    bs.out = static_cast<double*>(out);
-    set_limits(bs, b->L->store.dev, b->Ltmp.tmp.dev, b->n_elem, b->R->store.dev, b->Rtmp.tmp.dev);
-    hipStream_t vs[kNumVariants];
-    fork_variants(ctx, vs);
+    b64.X[0] = b64.X[1] = static_cast<const double*>(psi);
+    b64.out = static_cast<double*>(out);
     int mode = ctx->fp64_kernel;
     if (mode == kFp64RingDword) {  // no buffer lengths known: the ring kernel moves single dwords
-      for (int i = 0; i < 6; ++i) bs.lim[i] = 0;
+      for (int i = 0; i < 6; ++i) b64.lim[i] = 0;
       mode = kFp64Ring;
     }
-    HCHECK(launch_mfma_f64(tl, b->mwork.ws, tk, bs, vs, ev, mode));
-    join_variants(ctx);
-  } else if (prec == HEFF_FP32) {
-    if (!(b->prec_mask & (1u << HEFF_FP32))) throw Error(HEFF_ENOTSUP, "FP32 operands were not built");
-    Bases<float> bs{};
-    bs.L[0] = b->f32[0].as<float>();
-    bs.L[1] = b->f32[1].as<float>();
-    bs.R[0] = b->f32[2].as<float>();
-    bs.R[1] = b->f32[3].as<float>();
-    bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
-    bs.out = static_cast<float*>(out);
-    hipStream_t vs[kNumVariants];
     fork_variants(ctx, vs);
-    HCHECK(launch_mfma_f32(tl, b->mwork.ws, tk, bs, vs, ev));
+    HCHECK(launch_mfma_f64(tl, ws, tk, b64, vs, ev, mode));
     join_variants(ctx);
-  } else if (prec == HEFF_BF16X3) {
-    if (!(b->prec_mask & (1u << HEFF_BF16X3))) throw Error(HEFF_ENOTSUP, "BF16X3 operands were not built");
-    Bases<float> bs{};
-    bs.L[0] = b->f32[0].as<float>();
-    bs.L[1] = b->f32[1].as<float>();
-    bs.R[0] = b->f32[2].as<float>();
-    bs.R[1] = b->f32[3].as<float>();
-    bs.X[0] = bs.X[1] = static_cast<const float*>(psi);
-    bs.out = static_cast<float*>(out);
-    hipStream_t vs[kNumVariants];
+  } else if (prec == HEFF_FP32 || prec == HEFF_BF16X3) {
+    if (!(prec_mask & (1u << prec)))
+      throw Error(HEFF_ENOTSUP, prec == HEFF_FP32 ? "FP32 operands were not built" : "BF16X3 operands were not built");
+    b32.X[0] = b32.X[1] = static_cast<const float*>(psi);
+    b32.out = static_cast<float*>(out);
     fork_variants(ctx, vs);
-    HCHECK(launch_bf16x3(tl, b->mwork.ws, tk, bs, vs, ev));
+    if (prec == HEFF_FP32) HCHECK(launch_mfma_f32(tl, ws, tk, b32, vs, ev));
+    else HCHECK(launch_bf16x3(tl, ws, tk, b32, vs, ev));
     join_variants(ctx);
   } else {
     throw Error(HEFF_EINVAL, "unknown precision");
   }
+}
+}  // namespace heff
+
+extern "C" int heff_apply(heff_ctx* ctx, const heff_blocks* b, int prec, const void* psi, void* out) {
+  if (!ctx) return HEFF_EINVAL;
+  ABI_BEGIN
+  if (!b || !psi || !out) throw Error(HEFF_EINVAL, "null argument");
+  if (psi == out) throw Error(HEFF_EINVAL, "psi and out alias");
+  HCHECK(hipSetDevice(ctx->device));
+  Bases<double> b64{};
+  b64.L[0] = b->L->store.dev.as<double>();
+  b64.L[1] = b->Ltmp.tmp.dev.as<double>();
+  b64.R[0] = b->R->store.dev.as<double>();
+  b64.R[1] = b->Rtmp.tmp.dev.as<double>();
+  set_limits(b64, b->L->store.dev, b->Ltmp.tmp.dev, b->n_elem, b->R->store.dev, b->Rtmp.tmp.dev);
+  Bases<float> b32{};
+  b32.L[0] = b->f32[0].as<float>();
+  b32.L[1] = b->f32[1].as<float>();
+  b32.R[0] = b->f32[2].as<float>();
+  b32.R[1] = b->f32[3].as<float>();
+  run_product(ctx, b->d_tiles.as<Tile>(), b->d_tasks.as<Task>(), b->mwork.ws, prec, b->prec_mask, b64, b32, psi, out);
   ABI_END(ctx)
 }
 

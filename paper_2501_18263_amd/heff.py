@@ -44,6 +44,25 @@ class _Problem(ctypes.Structure):
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_F64P = ctypes.POINTER(ctypes.c_double)
+
+
+class _Su2Block(ctypes.Structure):
+    _fields_ = [("n_sect", ctypes.c_int32), ("n", _I32P), ("two_s", _I32P), ("dim", _I32P),
+                ("n_ops", ctypes.c_int32), ("two_k", _I32P), ("dn", _I32P),
+                ("n_blk", ctypes.c_int64), ("blk_op", _I32P), ("blk_out", _I32P), ("blk_in", _I32P),
+                ("blk_off", _I64P), ("data", _F64P), ("data_len", ctypes.c_int64)]
+
+
+class _Su2Problem(ctypes.Structure):
+    _fields_ = [("left", _Su2Block), ("right", _Su2Block), ("n_terms", ctypes.c_int32),
+                ("term_l", _I32P), ("term_site_k", _I32P), ("term_site_k1", _I32P), ("term_r", _I32P),
+                ("term_two_s", _I32P), ("term_coef", _F64P), ("n_tot", ctypes.c_int32), ("two_s_tot", ctypes.c_int32)]
+
+
+
 # heff_alloc: device memory provider callbacks
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -156,6 +175,12 @@ _lib.heff_batch_apply.argtypes = [_vp, _vp, _i]
 _lib.heff_batch_free.argtypes = [_vp]
 _lib.heff_debug_op.argtypes = [_vp, _i, _i, _i, _i, ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
 _lib.heff_debug_op.restype = ctypes.c_int64
+_lib.heff_su2_create.argtypes = [_vp, ctypes.POINTER(_Su2Problem), ctypes.c_uint32, ctypes.POINTER(_vp)]
+_lib.heff_su2_layout.argtypes = [_vp, _I64P, _I32P, ctypes.POINTER(_I32P), ctypes.POINTER(_I64P)]
+_lib.heff_su2_stats.argtypes = [_vp, _I64P, _F64P, _F64P]
+_lib.heff_su2_apply.argtypes = [_vp, _vp, _i, _vp, _vp]
+_lib.heff_su2_free.argtypes = [_vp]
+_lib.heff_su2_factor.argtypes = [_I32P, _F64P]
 
 EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks", "heff_validate_problem",
             "heff_blocks_free",
@@ -166,7 +191,8 @@ EXPORTED = ("heff_create", "heff_destroy", "heff_last_error", "heff_build_blocks
             "heff_sweep_right", "heff_start_vector", "heff_rotate_pair", "heff_pair_entropy",
             "heff_optimize_pair", "heff_rotate_integrals",
             "heff_batch_layout", "heff_batch_create", "heff_batch_io", "heff_batch_set_grid", "heff_batch_stats",
-            "heff_batch_apply", "heff_batch_free")
+            "heff_batch_apply", "heff_batch_free", "heff_su2_create", "heff_su2_layout", "heff_su2_stats",
+            "heff_su2_apply", "heff_su2_free", "heff_su2_factor")
 N_VARIANTS = 4
 FP64_AUTO, FP64_STAGED, FP64_RING, FP64_RING_DWORD = 0, 1, 2, 3
 
@@ -750,3 +776,115 @@ def heff_energy_function():
     if _HE is None:
         _HE = _energy_function()
     return _HE
+
+
+# --------------------------------------------------------------------------
+# SU(2) spin-adapted product
+# --------------------------------------------------------------------------
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_I32P)
+
+
+def _su2_block(blk, keep):
+    """heff_su2_block from a synth_su2 Block (arrays kept alive in keep)."""
+    from . import synth_su2
+    sec = np.array(blk.sectors, dtype=np.int32).reshape(-1, 3)
+    cols = [np.ascontiguousarray(sec[:, j]) for j in range(3)]
+    two_k = np.array([op[0] for op in blk.ops], dtype=np.int32)
+    dn = np.array([op[1] for op in blk.ops], dtype=np.int32)
+    bop, bout, bin_, boff, data = synth_su2.op_arrays(blk)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    boff = np.ascontiguousarray(boff, dtype=np.int64)
+    keep += cols + [two_k, dn, bop, bout, bin_, boff, data]
+    b = _Su2Block()
+    b.n_sect = len(blk.sectors)
+    b.n, b.two_s, b.dim = (c.ctypes.data_as(_I32P) for c in cols)
+    b.n_ops = len(blk.ops)
+    b.two_k, b.dn = two_k.ctypes.data_as(_I32P), dn.ctypes.data_as(_I32P)
+    b.n_blk = len(bop)
+    b.blk_op, b.blk_out, b.blk_in = (x.ctypes.data_as(_I32P) for x in (bop, bout, bin_))
+    b.blk_off = boff.ctypes.data_as(_I64P)
+    b.data = data.ctypes.data_as(_F64P)
+    b.data_len = data.size
+    return b
+
+
+def _su2_marshal(problem, keep):
+    pr = _Su2Problem()
+    pr.left = _su2_block(problem.L, keep)
+    pr.right = _su2_block(problem.R, keep)
+    t = problem.terms
+    cols = [np.array([x[j] for x in t], dtype=np.int32) for j in range(5)]
+    coef = np.array([x[5] for x in t], dtype=np.float64)
+    keep += cols + [coef]
+    pr.n_terms = len(t)
+    pr.term_l, pr.term_site_k, pr.term_site_k1, pr.term_r, pr.term_two_s = (c.ctypes.data_as(_I32P) for c in cols)
+    pr.term_coef = coef.ctypes.data_as(_F64P)
+    pr.n_tot, pr.two_s_tot = problem.n_tot, problem.ts_tot
+    return pr
+
+
+def su2_factor(two_j):
+    """F(a, b, c; k_a, k_b, k_c; a', b', c') of doubled spins (host only)."""
+    arr, ptr = _i32(list(two_j))
+    if arr.size != 9:
+        raise ValueError("nine doubled spins")
+    f = ctypes.c_double()
+    rc = _lib.heff_su2_factor(ptr, ctypes.byref(f))
+    if rc != 0:
+        raise HeffError(rc, "heff_su2_factor")
+    return f.value
+
+
+class Su2:
+    """SU(2) spin-adapted two-site product of a synth_su2 problem."""
+
+    def __init__(self, ctx: Context, problem, precs=(FP64,)):
+        self.ctx = ctx
+        keep = []
+        pr = _su2_marshal(problem, keep)
+        mask = 0
+        for p in precs:
+            mask |= 1 << p
+        out = _vp()
+        ctx.check(_lib.heff_su2_create(ctx._h, ctypes.byref(pr), mask, ctypes.byref(out)))
+        self._h = out
+        n = ctypes.c_int64()
+        nb = ctypes.c_int32()
+        desc = _I32P()
+        offs = _I64P()
+        ctx.check(_lib.heff_su2_layout(out, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(desc), ctypes.byref(offs)))
+        self.n_elem = n.value
+        self.blocks = [(tuple(desc[8 * i + j] for j in range(6)), offs[i], desc[8 * i + 6], desc[8 * i + 7])
+                       for i in range(nb.value)]
+
+    def stats(self):
+        nt = ctypes.c_int64()
+        fl = ctypes.c_double()
+        nr = ctypes.c_double()
+        self.ctx.check(_lib.heff_su2_stats(self._h, ctypes.byref(nt), ctypes.byref(fl), ctypes.byref(nr)))
+        return dict(n_tasks=nt.value, flops=fl.value, n_resolved=nr.value)
+
+    def apply(self, psi, out, prec=FP64):
+        import torch
+        want = torch.float64 if prec == FP64 else torch.float32
+        if psi.dtype != want or out.dtype != want or psi.numel() != self.n_elem or out.numel() != self.n_elem:
+            raise ValueError("psi/out must be %s tensors of %d elements" % (want, self.n_elem))
+        if not (psi.is_cuda and out.is_cuda and psi.is_contiguous() and out.is_contiguous()):
+            raise ValueError("psi/out must be contiguous device tensors")
+        self.ctx.check(_lib.heff_su2_apply(self.ctx._h, self._h, prec, _ptr(psi), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.heff_su2_free(self._h)
+            self._h = None
+
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -179,20 +179,25 @@ def small_problem(seed=1, dmax=3):
     return make_problem(seed, Ls, Rs, 8, 8, 60, 4, 0)
 
 
-def bench_problem(seed=3, d_scale=1.0):
-    """A larger problem: blocks of 9..15 electrons with spins up to 9/2 and
-    sector dimensions shaped like a truncated MPS bond (largest near the
-    middle particle number and low spin)."""
+def bench_problem(seed=3, d_scale=1.0, n_terms=1500):
+    """The benchmark problem: blocks of 4..20 electrons with spins up to
+    11/2 and multiplet dimensions shaped like a truncated bond (largest at 12
+    electrons and low spin, at most 256): 75 sectors, 2692 multiplets per
+    block (10645 states with the magnetic quantum number resolved, the
+    compression the paper quotes for its largest SU(2) runs), 48 random
+    operators per block, 26 electrons in a singlet."""
     rng = np.random.default_rng(seed + 500)
 
-    def secs(n_range, n_mid):
+    def secs():
         out = []
-        for n in n_range:
-            for ts in range(n % 2, min(n, 9) + 1, 2):
-                w = np.exp(-0.5 * ((n - n_mid) / 1.6) ** 2 - 0.35 * ts)
-                out.append((n, ts, max(1, int(round(d_scale * 140 * w * (0.8 + 0.4 * rng.random()))))))
+        for n in range(4, 21):
+            for ts in range(n % 2, min(n, 11) + 1, 2):
+                w = np.exp(-0.5 * ((n - 12) / 2.2) ** 2 - 0.25 * ts)
+                d = int(round(d_scale * 230 * w * (0.8 + 0.4 * rng.random())))
+                if d >= 1:
+                    out.append((n, ts, min(d, 256)))
         return out
 
-    Ls = secs(range(8, 17), 12)
-    Rs = secs(range(8, 17), 12)
-    return make_problem(seed, Ls, Rs, 48, 48, 1500, 26, 0)
+    Ls = secs()
+    Rs = secs()
+    return make_problem(seed, Ls, Rs, 48, 48, n_terms, 26, 0)

@@ -13,6 +13,13 @@
 // int32 n_right; per right bond likewise;
 // int32 n_iso_left; per isometry: int64 len, double[len];
 // int32 n_iso_right; per isometry likewise.
+//
+// SU(2) mode (``--su2 file``): "HEFFSU21", int32 count, then per problem two
+// blocks (int32 n_sect; int32 n[], two_s[], dim[]; int32 n_ops; int32
+// two_k[], dn[]; int64 n_blk; int32 op[], out[], in[]; int64 off[]; int64
+// data_len; double data[]), int32 n_terms; int32 l[], site_k[], site_k1[],
+// r[], two_s[]; double coef[]; int32 n_tot, two_s_tot.  Each problem is
+// created with FP32 operands and applied in every precision.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -91,9 +98,104 @@ int fail(heff_ctx* ctx, const char* what, int rc) {
   return 1;
 }
 
+struct Su2Block {
+  std::vector<int32_t> n, ts, dim, two_k, dn, op, out, in;
+  std::vector<int64_t> off;
+  std::vector<double> data;
+  heff_su2_block b{};
+};
+
+void read_su2_block(Reader& r, Su2Block& d) {
+  const int32_t ns = r.get<int32_t>();
+  r.arr(d.n, ns);
+  r.arr(d.ts, ns);
+  r.arr(d.dim, ns);
+  const int32_t no = r.get<int32_t>();
+  r.arr(d.two_k, no);
+  r.arr(d.dn, no);
+  const int64_t nb = r.get<int64_t>();
+  r.arr(d.op, nb);
+  r.arr(d.out, nb);
+  r.arr(d.in, nb);
+  r.arr(d.off, nb);
+  r.arr(d.data, (size_t)r.get<int64_t>());
+  d.b = {ns, d.n.data(), d.ts.data(), d.dim.data(), no, d.two_k.data(), d.dn.data(), nb, d.op.data(), d.out.data(),
+         d.in.data(), d.off.data(), d.data.data(), (int64_t)d.data.size()};
+}
+
+int run_su2(const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) { std::perror(path); return 2; }
+  Reader r{f};
+  char magic[8];
+  if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "HEFFSU21", 8) != 0) {
+    std::fprintf(stderr, "not an SU(2) problem file\n");
+    return 2;
+  }
+  heff_ctx* ctx = nullptr;
+  int rc = heff_create(&ctx, 0, nullptr, nullptr);
+  if (rc) return fail(nullptr, "heff_create", rc);
+  const int32_t count = r.get<int32_t>();
+  long long n_tasks = 0;
+  double flops = 0.0;
+  for (int i = 0; i < count; ++i) {
+    Su2Block L, R;
+    read_su2_block(r, L);
+    read_su2_block(r, R);
+    const int32_t nt = r.get<int32_t>();
+    std::vector<int32_t> tl, tk, tk1, tr, tts;
+    std::vector<double> tc;
+    r.arr(tl, nt);
+    r.arr(tk, nt);
+    r.arr(tk1, nt);
+    r.arr(tr, nt);
+    r.arr(tts, nt);
+    r.arr(tc, nt);
+    heff_su2_problem p{};
+    p.left = L.b;
+    p.right = R.b;
+    p.n_terms = nt;
+    p.term_l = tl.data();
+    p.term_site_k = tk.data();
+    p.term_site_k1 = tk1.data();
+    p.term_r = tr.data();
+    p.term_two_s = tts.data();
+    p.term_coef = tc.data();
+    p.n_tot = r.get<int32_t>();
+    p.two_s_tot = r.get<int32_t>();
+    heff_su2* h = nullptr;
+    if ((rc = heff_su2_create(ctx, &p, (1u << HEFF_FP32) | (1u << HEFF_BF16X3), &h))) return fail(ctx, "heff_su2_create", rc);
+    int64_t ne = 0, tasks = 0;
+    double fl = 0.0, nres = 0.0;
+    heff_su2_layout(h, &ne, nullptr, nullptr, nullptr);
+    heff_su2_stats(h, &tasks, &fl, &nres);
+    n_tasks += tasks;
+    flops += fl;
+    void *x = nullptr, *y = nullptr;
+    hipMalloc(&x, (size_t)ne * 8);
+    hipMalloc(&y, (size_t)ne * 8);
+    for (int prec : {HEFF_FP64, HEFF_FP32, HEFF_BF16X3})
+      if ((rc = heff_su2_apply(ctx, h, prec, x, y))) return fail(ctx, "heff_su2_apply", rc);
+    hipFree(x);
+    hipFree(y);
+    heff_su2_free(h);
+  }
+  std::fclose(f);
+  heff_destroy(ctx);
+  long viol, launches, items, tasks, live_allocs;
+  size_t peak, live;
+  hostcheck_report(&viol, &launches, &items, &tasks, &peak, &live, &live_allocs);
+  std::printf("{\"problems\": %d, \"tasks\": %lld, \"flops\": %.6e, \"launches\": %ld, \"work_items_checked\": %ld, "
+              "\"tasks_checked\": %ld, \"violations\": %ld, \"peak_device_bytes\": %zu, \"leaked_bytes\": %zu, "
+              "\"leaked_allocations\": %ld}\n",
+              count, n_tasks, flops, launches, items, tasks, viol, peak, live, live_allocs);
+  return viol ? 1 : 0;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
+  if (argc == 3 && std::strcmp(argv[1], "--su2") == 0) return run_su2(argv[2]);
   if (argc < 2) {
     std::fprintf(stderr, "usage: %s problems.bin [--no-single]\n", argv[0]);
     return 2;

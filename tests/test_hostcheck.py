@@ -24,6 +24,7 @@ from paper_2501_18263_amd import synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HC = os.path.join(ROOT, "tests", "hostcheck")
 SRC = [os.path.join(ROOT, "paper_2501_18263_amd", "csrc", "heff_host.hip"),
+       os.path.join(ROOT, "paper_2501_18263_amd", "csrc", "heff_su2.hip"),
        os.path.join(HC, "hostcheck_runtime.cpp"), os.path.join(HC, "hostcheck_main.cpp")]
 
 
@@ -33,7 +34,7 @@ def build_hostcheck(out_dir):
     exe = os.path.join(out_dir, "hostcheck")
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-I" + HC, "-I" + os.path.join(ROOT, "paper_2501_18263_amd", "csrc"), "-I" + os.path.join(ROOT, "include"),
-           "-x", "c++", SRC[0], "-x", "none", SRC[1], SRC[2], "-o", exe, "-lpthread"]
+           "-x", "c++", SRC[0], SRC[1], "-x", "none", SRC[2], SRC[3], "-o", exe, "-lpthread"]
     subprocess.check_call(cmd)
     return exe
 
@@ -106,3 +107,57 @@ def test_hostcheck_batch_sample(exe, tmp_path):
     write_problems(path, probs)
     s = _summary(run_hostcheck(exe, path, single=False))
     assert s["violations"] == 0 and s["leaked_bytes"] == 0 and s["leaked_allocations"] == 0
+
+
+def write_su2_problems(path, problems):
+    """SU(2) problem file of the driver (format in hostcheck_main.cpp)."""
+    from paper_2501_18263_amd import synth_su2
+    with open(path, "wb") as f:
+        f.write(b"HEFFSU21")
+        f.write(struct.pack("<i", len(problems)))
+        for p in problems:
+            for blk in (p.L, p.R):
+                sec = np.array(blk.sectors, dtype="<i4").reshape(-1, 3)
+                f.write(struct.pack("<i", len(sec)))
+                for j in range(3):
+                    f.write(np.ascontiguousarray(sec[:, j]).tobytes())
+                f.write(struct.pack("<i", len(blk.ops)))
+                f.write(np.array([op[0] for op in blk.ops], dtype="<i4").tobytes())
+                f.write(np.array([op[1] for op in blk.ops], dtype="<i4").tobytes())
+                bop, bout, bin_, boff, data = synth_su2.op_arrays(blk)
+                f.write(struct.pack("<q", len(bop)))
+                for a in (bop, bout, bin_):
+                    f.write(a.astype("<i4").tobytes())
+                f.write(boff.astype("<i8").tobytes())
+                f.write(struct.pack("<q", data.size))
+                f.write(data.astype("<f8").tobytes())
+            f.write(struct.pack("<i", len(p.terms)))
+            for j in range(5):
+                f.write(np.array([t[j] for t in p.terms], dtype="<i4").tobytes())
+            f.write(np.array([t[5] for t in p.terms], dtype="<f8").tobytes())
+            f.write(struct.pack("<ii", p.n_tot, p.ts_tot))
+
+
+def test_hostcheck_su2(exe, tmp_path):
+    # the SU(2) product's validation, layout and task table on small and
+    # medium problems (every spin total up to 3/2, dimensions up to 70 so
+    # that output blocks span two 64-row work items), launched in every
+    # precision through the checkers
+    from paper_2501_18263_amd import synth_su2 as S
+    probs = []
+    for seed, (n_tot, ts) in enumerate([(4, 0), (4, 2), (3, 1), (5, 3)]):
+        p = S.small_problem(seed + 1)
+        p.n_tot, p.ts_tot = n_tot, ts
+        probs.append(p)
+    rng = np.random.default_rng(9)
+    Ls = S.sectors(rng, range(2, 7), 5, 70, 20)
+    Rs = S.sectors(rng, range(2, 7), 5, 70, 20)
+    probs.append(S.make_problem(9, Ls, Rs, 16, 16, 120, 9, 1))
+    path = str(tmp_path / "su2.bin")
+    write_su2_problems(path, probs)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe, "--su2", path], capture_output=True, text=True, timeout=600, env=env)
+    s = _summary(r)
+    assert s["violations"] == 0 and s["leaked_bytes"] == 0 and s["leaked_allocations"] == 0
+    assert s["tasks"] > 0 and s["work_items_checked"] > 0 and s["tasks_checked"] > 0
