@@ -431,6 +431,42 @@ static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
   tasks.swap(nk);
 }
 
+// Tiles whose output fits the 128-wide kernel (e <= 128) but which have a
+// task with a middle dimension c above 128 would need the 256-wide kernel
+// (it holds T = op(L) op(X) with c columns in registers).  Such tasks are
+// split into ranges of c of at most 128 instead: the ranges' partial
+// products follow each other in the output-stationary accumulation, in the
+// order the unsplit task would add them, so the sums are unchanged, and the
+// tile runs on the 128-wide kernel (two work-groups per CU, no spills)
+// at the cost of reading its op(L) slices once per range.
+void split_wide_c(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
+  constexpr int kWide = 128;
+  bool any = false;
+  for (const Tile& t : tiles) {
+    if (t.e > kWide) continue;
+    for (int k = t.t0; k < t.t1 && !any; ++k) any = tasks[k].c > kWide;
+    if (any) break;
+  }
+  if (!any) return;
+  std::vector<Task> nk;
+  nk.reserve(tasks.size() + tasks.size() / 8);
+  for (Tile& t : tiles) {
+    const int t0 = (int)nk.size();
+    for (int k = t.t0; k < t.t1; ++k) {
+      const Task& s = tasks[k];
+      if (t.e > kWide || s.c <= kWide || (s.flags & T_IDR)) {
+        nk.push_back(s);
+        continue;
+      }
+      for (int m0 = 0; m0 < s.c; m0 += kWide) nk.push_back(restrict_c(s, m0, std::min(kWide, s.c - m0)));
+    }
+    t.t0 = t0;
+    t.t1 = (int)nk.size();
+  }
+  if (nk.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
+  tasks.swap(nk);
+}
+
 // Largest dimension a tile's kernels hold in registers: the output width e
 // and the middle dimension c of its tasks (T = op(L) op(X) has c columns).
 int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
@@ -1302,6 +1338,7 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
     d.t1 = (int32_t)dtasks.size();
     dtiles[y] = d;
   }
+  split_wide_c(tiles, tasks);
   // largest output blocks first (longest work items start early)
   std::vector<int> order(nb);
   for (int i = 0; i < nb; ++i) order[i] = i;

@@ -346,6 +346,9 @@ static void build(heff_ctx* ctx, const heff_su2_problem* p, uint32_t prec_mask, 
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
   for (const Task& k : tasks) H.flops += task_flops(k);
   H.n_tasks = (int64_t)tasks.size();
+  // (no split_wide_c here: on the SU(2) benchmark problem, whose longest
+  // output blocks gather thousands of tasks with narrow op(L), splitting
+  // the middle dimension measured 5 % slower)
   std::vector<int> order(nb);
   for (int i = 0; i < nb; ++i) order[i] = i;
   std::vector<Work> lists[kNumVariants];

@@ -276,9 +276,11 @@ WIDE_BARS = (5e-5, 5e-5)
 
 def test_apply_wide_variants_match_oracle(heff, ctx):
     # Random isometries at a size whose blocks reach the 128- and 256-wide
-    # kernel variants (N=14, D=1024, beta=1: sectors up to 170 wide), the
-    # whole output element by element against O-BLOCK; FP32 and the bf16
-    # split against the same oracle output.
+    # kernel variants (N=14, D=1024, beta=1: sectors up to 170 wide; outputs
+    # at most 128 wide with tasks of a middle dimension above 128 run those
+    # tasks split into ranges of it), the whole output element by element
+    # against O-BLOCK; FP32 and the bf16 split against the same oracle
+    # output.
     p = synth.make_problem(14, 1024, 2, beta=1.0)
     print("case N=14 D=1024 seed=2 beta=1 random isometries", flush=True)
     B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32, heff.BF16X3))

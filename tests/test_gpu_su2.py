@@ -79,6 +79,24 @@ def test_su2_product_medium_all_precisions(heff, ctx):
         assert err <= bar
 
 
+def test_su2_product_wide_middle_dimension(heff, ctx):
+    # right sectors up to 200 wide beside narrow ones: outputs at most 128
+    # wide whose tasks have a middle dimension above 128 (the 256-wide
+    # kernel instance); element-wise vs the task form
+    rng = np.random.default_rng(10)
+    Ls = S.sectors(rng, range(2, 5), 3, 24, 4)
+    Rs = [(2, 0, 200), (2, 2, 40), (3, 1, 150), (3, 3, 20), (4, 0, 90), (4, 2, 130)]
+    p = S.make_problem(11, Ls, Rs, 12, 12, 60, 7, 1)
+    print("case wide middle dimension", flush=True)
+    H = heff.Su2(ctx, p, precs=(heff.FP64, heff.FP32))
+    x = S.random_psi(p, seed=4)
+    y0 = su2.apply_tasks(p, x)
+    y = _run(heff, H, x, heff.FP64)
+    assert np.abs(y - y0).max() <= 1e-12 * np.abs(y0).max()
+    yr = _run(heff, H, x, heff.FP32)
+    assert np.linalg.norm(yr - y0) / np.linalg.norm(y0) <= 1e-5
+
+
 def test_su2_product_benchmark_size_sampled(heff, ctx):
     # the benchmark problem (75 sectors, 2692 multiplets per block, 1500
     # terms): output blocks sampled (the two largest and six random)

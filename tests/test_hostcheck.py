@@ -153,6 +153,12 @@ def test_hostcheck_su2(exe, tmp_path):
     Ls = S.sectors(rng, range(2, 7), 5, 70, 20)
     Rs = S.sectors(rng, range(2, 7), 5, 70, 20)
     probs.append(S.make_problem(9, Ls, Rs, 16, 16, 120, 9, 1))
+    # right sectors up to 200 wide next to narrow ones: tasks with a middle
+    # dimension above 128 into outputs at most 128 wide
+    rng = np.random.default_rng(10)
+    Ls = S.sectors(rng, range(2, 5), 3, 24, 4)
+    Rs = [(2, 0, 200), (2, 2, 40), (3, 1, 150), (3, 3, 20), (4, 0, 90), (4, 2, 130)]
+    probs.append(S.make_problem(11, Ls, Rs, 12, 12, 60, 7, 1))
     path = str(tmp_path / "su2.bin")
     write_su2_problems(path, probs)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
