@@ -766,6 +766,61 @@ def _energy_function():
     return HeffEnergy
 
 
+def _integral_energy_function():
+    import dataclasses
+
+    import torch
+
+    class HeffIntegralEnergy(torch.autograd.Function):
+        """E = <psi|H_eff(h, V)|psi> as a differentiable function of psi and
+        of the integrals h (n x n) and V (n^4, (ij|kl)); the isometries of
+        `problem` are held fixed.  The forward builds the blocks from h and
+        V; the backward gives dE/dpsi = 2 H_eff psi and, when asked for,
+        dE/dh and dE/dV by heff_integral_gradient (the one- and half the
+        two-particle density matrix of the state: exact, one build per
+        symmetry orbit of integral indices, meant for small orbital counts).
+        Usage: HeffIntegralEnergy.apply(psi, h, V, problem, context)."""
+
+        @staticmethod
+        def forward(ctx_, psi, h, V, problem, context):
+            hp = h.detach().double().cpu().numpy()
+            Vp = V.detach().double().cpu().numpy()
+            prob = dataclasses.replace(problem, h=hp, V=Vp)
+            B = Blocks(context, prob)
+            ctx_.blocks, ctx_.problem, ctx_.context = B, prob, context
+            ctx_.save_for_backward(psi, h, V)
+            return torch.tensor(B.energy(psi.detach()), dtype=torch.float64, device=psi.device)
+
+        @staticmethod
+        def backward(ctx_, gE):
+            psi, h, V = ctx_.saved_tensors
+            g = float(gE)
+            dpsi = dh = dV = None
+            if ctx_.needs_input_grad[0]:
+                dpsi, _, _ = ctx_.blocks.energy_backward(psi.detach(), g, FP64, ops=False)
+            nh, nv = ctx_.needs_input_grad[1], ctx_.needs_input_grad[2]
+            if nh or nv:
+                gh, gV = integral_gradient(ctx_.context, ctx_.problem, psi.detach(), one_body=nh, two_body=nv)
+                if nh:
+                    dh = torch.as_tensor(g * gh, dtype=h.dtype, device=h.device)
+                if nv:
+                    dV = torch.as_tensor(g * gV, dtype=V.dtype, device=V.device)
+            return dpsi, dh, dV, None, None
+
+    return HeffIntegralEnergy
+
+
+_HIE = None
+
+
+def heff_integral_energy_function():
+    """The torch.autograd.Function of E(psi, h, V) (created lazily)."""
+    global _HIE
+    if _HIE is None:
+        _HIE = _integral_energy_function()
+    return _HIE
+
+
 _HE = None
 
 

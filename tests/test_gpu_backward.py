@@ -217,3 +217,37 @@ def test_integral_gradient_one_body_n6(heff, ctx):
     assert gV is None
     ref = grad.one_rdm(p, psi)
     assert np.abs(gh - ref).max() <= 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_integral_energy_autograd_n4(heff, ctx):
+    # E(psi, h, V) with the integrals as autograd inputs: the gradients
+    # agree with the oracle's density matrices, and, E being linear in h and
+    # V, a finite step of the integrals changes E by exactly the gradient's
+    # inner product with it
+    p = synth.make_problem(4, 400, 3)
+    print("case integral-energy autograd N=4 seed=3", flush=True)
+    psi = np.random.default_rng(5).standard_normal(synth.psi_size(p))
+    f = heff.heff_integral_energy_function()
+    x = _dev(psi).requires_grad_(True)
+    h = torch.tensor(p.h, requires_grad=True)
+    V = torch.tensor(p.V, requires_grad=True)
+    E = f.apply(x, h, V, p, ctx)
+    E.backward()
+    rh, rV = grad.integral_gradient(p, psi)
+    scale = max(1.0, np.abs(rh).max())
+    assert np.abs(h.grad.numpy() - rh).max() <= 1e-10 * scale
+    assert np.abs(V.grad.numpy() - rV).max() <= 1e-10 * scale
+    B = heff.Blocks(ctx, p)
+    hx = torch.empty_like(x)
+    B.apply(x.detach(), hx)
+    assert float((x.grad - 2 * hx).abs().max()) <= 1e-12 * float(hx.abs().max())
+    rng = np.random.default_rng(8)
+    dh = rng.standard_normal(p.h.shape) * 1e-2
+    dh = dh + dh.T
+    d0 = rng.standard_normal(p.V.shape) * 1e-3
+    dV = sum(d0.transpose(t) for t in ((0, 1, 2, 3), (1, 0, 2, 3), (0, 1, 3, 2), (1, 0, 3, 2),
+                                       (2, 3, 0, 1), (3, 2, 0, 1), (2, 3, 1, 0), (3, 2, 1, 0)))
+    with torch.no_grad():
+        E2 = f.apply(x.detach(), torch.tensor(p.h + dh), torch.tensor(p.V + dV), p, ctx)
+    pred = float(E) + float((h.grad * torch.tensor(dh)).sum() + (V.grad * torch.tensor(dV)).sum())
+    assert abs(float(E2) - pred) <= 1e-10 * max(1.0, abs(float(E)))
