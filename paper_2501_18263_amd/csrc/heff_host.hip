@@ -2187,21 +2187,7 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
   upload(dm, nrow, s);
   upload(dc, ncol, s);
   HCHECK(launch_identity(dwoff.as<int64_t>(), dm.as<int32_t>(), nq, WT.as<double>(), s));
-  // a row of B whose norm is below eps (m + c) ||M_Q'||_F is rounding of a
-  // zero singular value and takes no part in the rotations
   dsig.alloc((size_t)std::max<int64_t>(stot, 1) * sizeof(double));
-  HCHECK(launch_row_norms(dboff.as<int64_t>(), dm.as<int32_t>(), dc.as<int32_t>(), dsoff.as<int64_t>(), nq,
-                          Bm.as<double>(), dsig.as<double>(), s));
-  std::vector<double> sig(stot);
-  if (stot) HCHECK(hipMemcpyAsync(sig.data(), dsig.p, (size_t)stot * sizeof(double), hipMemcpyDeviceToHost, s));
-  HCHECK(hipStreamSynchronize(s));
-  std::vector<double> small2(nq, 0.0);
-  for (int q = 0; q < nq; ++q) {
-    double f2 = 0.0;
-    for (int i = 0; i < nrow[q]; ++i) f2 += sig[soff[q] + i] * sig[soff[q] + i];
-    const double z = 2.220446049250313e-16 * (nrow[q] + ncol[q]);
-    small2[q] = z * z * f2;
-  }
   // rounds of the block pair schedule, sweeps until every sector's rows are
   // orthogonal to rounding: |G_ij| <= eps sqrt(c) sqrt(G_ii G_jj), c the
   // length of a row (the one-sided Jacobi threshold of Demmel and Veselic)
@@ -2222,7 +2208,6 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
       j.K = K;
       j.pr = pr;
       j.sector = q;
-      j.small2 = small2[q];
       bj.push_back(j);
     }
   }
@@ -2249,6 +2234,7 @@ extern "C" int heff_truncate(heff_ctx* ctx, const heff_blocks* b, const double* 
   // singular values: row norms of B (at most min(rows, columns) non-zero)
   HCHECK(launch_row_norms(dboff.as<int64_t>(), dm.as<int32_t>(), dc.as<int32_t>(), dsoff.as<int64_t>(), nq,
                           Bm.as<double>(), dsig.as<double>(), s));
+  std::vector<double> sig(stot);
   if (stot) HCHECK(hipMemcpyAsync(sig.data(), dsig.p, (size_t)stot * sizeof(double), hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
   std::vector<std::vector<double>> lam(nq);

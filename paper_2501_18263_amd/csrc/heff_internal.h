@@ -156,7 +156,6 @@ struct BjJob {
   int32_t m, c;          // rows, columns of M
   int32_t K, pr;         // blocks of the schedule (even), pair index in a round
   int32_t sector, pad;
-  double small2;         // rows of B with squared norm <= small2 count as zero
 };
 // one round r of every job's schedule; off_max[sector] receives (as bits of
 // a non-negative double, atomic max) the largest |G_ij| / sqrt(G_ii G_jj)

@@ -1416,9 +1416,9 @@ __global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__
   __shared__ double buf[R2][CH + 1];
   __shared__ double cs[R2 / 2], sn[R2 / 2], dpp[R2 / 2], dqq[R2 / 2];
   __shared__ int pp[R2 / 2], qq[R2 / 2];
-  __shared__ int rows[R2], rank_of[R2];
+  __shared__ int rows[R2];
   __shared__ double red[256];
-  __shared__ int flag;
+  __shared__ int flag, rot;
   const BjJob jb = jobs[blockIdx.x];
   if (r >= jb.K - 1) return;
   int I, J;
@@ -1464,7 +1464,8 @@ __global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__
   for (int e = tid; e < nr * nr; e += 256) {
     const int i = e / nr, j = e % nr;
     if (i == j) continue;
-    if (G[i][i] > jb.small2 && G[j][j] > jb.small2) off = fmax(off, fabs(G[i][j]) / sqrt(G[i][i] * G[j][j]));
+    const double d = G[i][i] * G[j][j];
+    if (d > 1e-300) off = fmax(off, fabs(G[i][j]) / sqrt(d));
   }
   red[tid] = off;
   __syncthreads();
@@ -1477,17 +1478,18 @@ __global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__
     flag = red[0] > tol * sqrt((double)jb.c) ? 1 : 0;
   }
   __syncthreads();
+  // (the inner sweeps below keep their own flag: a thread still reading
+  // `flag` here must not see a later write)
   if (!flag) return;
   // eigenvectors of G: cyclic Jacobi, round-robin pairs; a pair is rotated
   // while |G_pq| > 1e-15 sqrt(G_pp G_qq) (relative to the pair's own scale,
-  // which keeps rows of very different norms accurate) and neither row is
-  // negligible (G_pp, G_qq above small2), until a sweep rotates nothing.
-  // The rotated 2 x 2 block is set from the closed form (G_pp - t G_pq,
-  // G_qq + t G_pq, 0), so that no rounding residue of the large diagonal
-  // entry stays in G_pq.
+  // which keeps rows of very different norms accurate), until a sweep
+  // rotates nothing (at most 40 sweeps).  The rotated 2 x 2 block is set
+  // from the closed form (G_pp - t G_pq, G_qq + t G_pq, 0), so that no
+  // rounding residue of the large diagonal entry stays in G_pq.
   const int P = (nr + 1) & ~1;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) flag = 0;
+    if (tid == 0) rot = 0;
     __syncthreads();
     for (int rr = 0; rr < P - 1; ++rr) {
       if (tid < P / 2) {
@@ -1495,14 +1497,14 @@ __global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__
         const int b = 1 + ((P - 1 - tid - 1 + rr) % (P - 1));
         const int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, sv = 0.0;
-        if (q < nr && fmin(G[p][p], G[q][q]) > jb.small2 && fabs(G[p][q]) > 1e-15 * sqrt(G[p][p] * G[q][q])) {
+        if (q < nr && fabs(G[p][q]) > 1e-15 * sqrt(G[p][p] * G[q][q])) {
           const double th = (G[q][q] - G[p][p]) / (2.0 * G[p][q]);
           const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           sv = t * c;
           dpp[tid] = G[p][p] - t * G[p][q];
           dqq[tid] = G[q][q] + t * G[p][q];
-          flag = 1;
+          rot = 1;
         }
         cs[tid] = c;
         sn[tid] = sv;
@@ -1542,26 +1544,11 @@ __global__ __launch_bounds__(256) void bj_round_kernel(const BjJob* __restrict__
       }
       __syncthreads();
     }
-    if (!flag) break;
+    if (!rot) break;
     __syncthreads();
   }
-  // eigenvectors in descending order of their eigenvalue: the pair's
-  // larger rows move to its lower block, which shortens the sweeps much
-  // like the row sorting of de Rijk's one-sided Jacobi
-  if (tid < nr) {
-    const double d = G[tid][tid];
-    int rk = 0;
-    for (int j = 0; j < nr; ++j) rk += (G[j][j] > d || (G[j][j] == d && j < tid)) ? 1 : 0;
-    rank_of[tid] = rk;
-  }
-  __syncthreads();
-  for (int e = tid; e < nr * nr; e += 256) {
-    const int k = e / nr, i = e % nr;
-    G[k][rank_of[i]] = Q[k][i];
-  }
-  __syncthreads();
-  rotate_rows(B, jb.c, rows, nr, G, buf);
-  rotate_rows(WT, m, rows, nr, G, buf);
+  rotate_rows(B, jb.c, rows, nr, Q, buf);
+  rotate_rows(WT, m, rows, nr, Q, buf);
 }
 
 hipError_t launch_bj_round(const BjJob* jobs, int n_jobs, double* B, double* WT, unsigned long long* off_max, int r,
