@@ -489,14 +489,30 @@ int tile_dim(const Tile& t, const std::vector<Task>& tasks) {
 // side).  Unused positions hold row0 = -1 (the kernels skip them).
 double task_flops(const Task& t);
 
+// Kernel variant that runs a tile.  When a task table has tiles for the
+// 128- or 256-wide kernels, its narrower tiles join the 128-wide kernel's
+// queue instead of running in kernels of their own beside it: one
+// longest-first queue keeps every CU on the wide work and fills the gaps
+// with the short narrow items (concurrent narrow kernels took CU slots
+// from the wide one's tail; N=40 D=4096: FP64 317 -> 300 ms, FP32 169 ->
+// 150 ms, bf16 split 136 -> 124 ms on one box).
+int launch_variant(const Tile& t, const std::vector<Task>& tasks, bool wide) {
+  const int v = variant_of(tile_dim(t, tasks));
+  return wide ? std::max(v, 2) : v;
+}
+bool has_wide(const std::vector<Tile>& tiles, const std::vector<Task>& tasks) {
+  for (const Tile& t : tiles)
+    if (variant_of(tile_dim(t, tasks)) >= 2) return true;
+  return false;
+}
+
 // Estimated run time of one 64-row work item of a tile, in units of one
 // 16x16x4 matrix instruction per wave: every pipeline step costs a fixed
 // overhead (loads, LDS traffic, barrier) of about kStepCost instructions
 // plus its matrix work, 4 ceil(c/16) instructions per stage-1 step and 4 NE
 // per stage-2 step (NE = the output-width bucket of the kernel instance).
-static double item_cost(const Tile& tile, const std::vector<Task>& tasks) {
+static double item_cost(const Tile& tile, const std::vector<Task>& tasks, int v) {
   constexpr double kStepCost = 8.0;
-  const int v = variant_of(tile_dim(tile, tasks));
   const int nt = 2 << v;
   const int ne = (tile.e + 15) / 16;
   int neb = nt;
@@ -513,14 +529,15 @@ static double item_cost(const Tile& tile, const std::vector<Task>& tasks) {
 void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks, const std::vector<int>& order,
                 std::vector<Work> (&lists)[kNumVariants], const std::vector<int>* key) {
   constexpr int kXcd = 8;
+  const bool wide = has_wide(tiles, tasks);
   std::vector<double> icost(tiles.size(), 0.0);
-  for (size_t t = 0; t < tiles.size(); ++t) icost[t] = item_cost(tiles[t], tasks);
+  for (size_t t = 0; t < tiles.size(); ++t) icost[t] = item_cost(tiles[t], tasks, launch_variant(tiles[t], tasks, wide));
   // groups per variant, in first-appearance order of `order`
   std::vector<std::vector<int>> groups[kNumVariants];
   std::vector<double> gcost[kNumVariants];
   std::map<std::pair<int, int>, int> gid;
   for (int t : order) {
-    const int v = variant_of(tile_dim(tiles[t], tasks));
+    const int v = launch_variant(tiles[t], tasks, wide);
     const double cost = icost[t] * std::max(1, (tiles[t].a + kTileRows - 1) / kTileRows);
     int g;
     if (key) {
@@ -1351,10 +1368,11 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   std::vector<Work> lists[kNumVariants];
   split_work(tiles, tasks, order, lists);
   B.mwork.upload_lists(lists, s);
+  const bool wide = has_wide(tiles, tasks);
   for (int y = 0; y < nb; ++y) {
     double fl = 0.0;
     for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
-    const int v = variant_of(tile_dim(tiles[y], tasks));
+    const int v = launch_variant(tiles[y], tasks, wide);
     B.vflops[v] += fl;
     // what the FP64/FP32 kernel issues: per active 16-row wave, 4 ceil(c/16)
     // MFMAs per stage-1 step (ceil(b/16) steps) and 4 ceil(e/16) per stage-2

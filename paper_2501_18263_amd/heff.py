@@ -25,6 +25,13 @@ K_H, K_C, K_A, K_B, K_T, K_D, K_DD, K_BB, K_S = range(9)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libheff.so is not built (run __graft_entry__.build()): " + LIB_PATH)
+# PyTorch is loaded before the library: its bundled HIP runtime then serves
+# the library's libamdhip64.so.7 dependency too.  Loaded the other way
+# round, the library binds the system runtime and PyTorch later loads its
+# own copy under another file name: two HIP runtimes in one process, and
+# the library's context creation fails on the GPU.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 

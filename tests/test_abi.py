@@ -53,3 +53,21 @@ def test_null_handles_are_rejected(lib):
     assert lib.heff_task_stats_issued(None, 0, ctypes.byref(d), ctypes.byref(n)) != 0
     assert lib.heff_apply(None, None, 0, None, None) != 0
     assert lib.heff_diag(None, None, None) != 0
+
+
+def test_binding_loads_one_hip_runtime():
+    # importing the binding first (before anything imports PyTorch) must
+    # leave a single HIP runtime in the process: the library's
+    # libamdhip64.so.7 dependency is served by PyTorch's bundled runtime.
+    # (Loaded the other way round, the system runtime and PyTorch's copy
+    # both load, and context creation then fails on the GPU.)
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2501_18263_amd import heff\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
