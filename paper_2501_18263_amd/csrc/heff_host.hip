@@ -385,22 +385,33 @@ static Task restrict_c(Task s, int m0, int w) {
   return s;
 }
 
-// Split output tiles wider than kMaxDim into column slices and tasks whose
-// middle dimension c exceeds kMaxDim into ranges of c (the partial products
-// add up in the output-stationary accumulation), so that every task fits
-// the register budget of the matrix-core kernels (they hold T = op(L) op(X)
-// with c columns; the inner dimension b is streamed and unbounded).
-static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
+// Split output tiles wider than max_dim into column slices and tasks whose
+// middle dimension c exceeds max_dim into ranges of c (the partial products
+// add up in the output-stationary accumulation, in the order the unsplit
+// task adds them, so every output element gets the same sum in the same
+// order), so that every task fits the register budget of a kernel instance
+// (it holds T = op(L) op(X) with c columns and the output rows' e columns;
+// the inner dimension b is streamed and unbounded).  The slices of one tile
+// are consecutive; parent, if given, receives each new tile's original
+// index.  Returns whether anything was split.
+bool split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks, int max_dim, std::vector<int>* parent) {
   bool any = false;
-  for (auto& t : tiles) any |= t.e > kMaxDim;
-  for (auto& k : tasks) any |= k.c > kMaxDim;
-  if (!any) return;
+  for (auto& t : tiles) any |= t.e > max_dim;
+  for (auto& k : tasks) any |= k.c > max_dim;
+  if (parent) {
+    parent->resize(tiles.size());
+    for (size_t i = 0; i < tiles.size(); ++i) (*parent)[i] = (int)i;
+  }
+  if (!any) return false;
   std::vector<Tile> nt;
   std::vector<Task> nk;
-  for (const Tile& t : tiles) {
-    for (int n0 = 0; n0 < std::max(t.e, 1); n0 += kMaxDim) {
+  nk.reserve(tasks.size() + tasks.size() / 4);
+  if (parent) parent->clear();
+  for (size_t ti = 0; ti < tiles.size(); ++ti) {
+    const Tile& t = tiles[ti];
+    for (int n0 = 0; n0 < std::max(t.e, 1); n0 += max_dim) {
       Tile u = t;
-      const int ew = std::max(std::min(kMaxDim, t.e - n0), 0);
+      const int ew = std::max(std::min(max_dim, t.e - n0), 0);
       u.offOut = t.offOut + n0;
       u.e = ew;
       u.t0 = (int32_t)nk.size();
@@ -417,54 +428,21 @@ static void split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
         }
         if (n0 > 0) s.offR += (s.flags & T_TR) ? (int64_t)n0 * s.ldR : n0;
         s.e = (uint16_t)ew;
-        if (s.c <= kMaxDim) {
+        if (s.c <= max_dim) {
           nk.push_back(s);
           continue;
         }
-        for (int m0 = 0; m0 < s.c; m0 += kMaxDim) nk.push_back(restrict_c(s, m0, std::min(kMaxDim, s.c - m0)));
+        for (int m0 = 0; m0 < s.c; m0 += max_dim) nk.push_back(restrict_c(s, m0, std::min(max_dim, s.c - m0)));
       }
       u.t1 = (int32_t)nk.size();
       nt.push_back(u);
+      if (parent) parent->push_back((int)ti);
     }
-  }
-  tiles.swap(nt);
-  tasks.swap(nk);
-}
-
-// Tiles whose output fits the 128-wide kernel (e <= 128) but which have a
-// task with a middle dimension c above 128 would need the 256-wide kernel
-// (it holds T = op(L) op(X) with c columns in registers).  Such tasks are
-// split into ranges of c of at most 128 instead: the ranges' partial
-// products follow each other in the output-stationary accumulation, in the
-// order the unsplit task would add them, so the sums are unchanged, and the
-// tile runs on the 128-wide kernel (two work-groups per CU, no spills)
-// at the cost of reading its op(L) slices once per range.
-void split_wide_c(std::vector<Tile>& tiles, std::vector<Task>& tasks) {
-  constexpr int kWide = 128;
-  bool any = false;
-  for (const Tile& t : tiles) {
-    if (t.e > kWide) continue;
-    for (int k = t.t0; k < t.t1 && !any; ++k) any = tasks[k].c > kWide;
-    if (any) break;
-  }
-  if (!any) return;
-  std::vector<Task> nk;
-  nk.reserve(tasks.size() + tasks.size() / 8);
-  for (Tile& t : tiles) {
-    const int t0 = (int)nk.size();
-    for (int k = t.t0; k < t.t1; ++k) {
-      const Task& s = tasks[k];
-      if (t.e > kWide || s.c <= kWide || (s.flags & T_IDR)) {
-        nk.push_back(s);
-        continue;
-      }
-      for (int m0 = 0; m0 < s.c; m0 += kWide) nk.push_back(restrict_c(s, m0, std::min(kWide, s.c - m0)));
-    }
-    t.t0 = t0;
-    t.t1 = (int)nk.size();
   }
   if (nk.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
+  tiles.swap(nt);
   tasks.swap(nk);
+  return true;
 }
 
 // Largest dimension a tile's kernels hold in registers: the output width e
@@ -606,7 +584,11 @@ void set_limits(Bases<double>& b, const DevBuf& l0, const DevBuf& l1, int64_t x,
 
 static void run_chain(ChainPlan& P, Bases<double> b, hipStream_t s) {
   if (P.tiles.empty()) return;
-  split_large(P.tiles, P.tasks);
+  // (the renormalization keeps tasks up to 256 wide: capped at 128 as the
+  // product is, the block build at N=40, D=4096 took 5.5 instead of 5.7 s
+  // with beta=1/2 and 5.8 instead of 6.8 s with beta=1, but the sweep
+  // step's Ren_l 1.03 instead of 0.98 s)
+  split_large(P.tiles, P.tasks, kMaxDim);
   DevBuf dt, dk;
   upload(dt, P.tiles, s);
   upload(dk, P.tasks, s);
@@ -1032,8 +1014,14 @@ struct heff_blocks {
   // product task table
   heff::DevBuf d_tiles, d_tasks, d_dtiles, d_dtasks;
   heff::DevWorkSet mwork;  // matrix-core work lists
-  std::vector<heff::Tile> h_tiles;  // host copies (used to assemble batches)
+  std::vector<heff::Tile> h_tiles;  // host copies (shards, batches)
   std::vector<heff::Task> h_tasks;
+  // when the product splits wide output blocks: the table with one tile
+  // per output block (the operand gradients use it) and each product
+  // tile's output block (empty: the tables coincide)
+  std::vector<heff::Tile> blk_tiles;
+  std::vector<heff::Task> blk_tasks;
+  std::vector<int> tile_blk;
   int64_t n_tiles = 0, n_tasks = 0, n_dtasks = 0;
   // ranks of the output-block shard the product is restricted to (1: the
   // full product); while > 1 the calls that need every output element
@@ -1355,10 +1343,25 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
     d.t1 = (int32_t)dtasks.size();
     dtiles[y] = d;
   }
-  split_wide_c(tiles, tasks);
+  // The product runs output blocks and middle dimensions of at most 128
+  // columns (column slices, ranges of c), so it never needs the 256-wide
+  // kernel instances, which hold one work-group per CU and spill (N=40,
+  // D=4096, beta=1, blocks up to 229 wide: FP64 1406 -> 924 ms, FP32 699 ->
+  // 464 ms, bf16 split 670 -> 372 ms on one box).  The operand gradients
+  // take every output block whole: they keep the unsplit table.
+  B.n_tasks = (int64_t)tasks.size();
+  bool wide_any = false;
+  for (const Tile& t : tiles) wide_any |= t.e > kProductDim;
+  for (const Task& k : tasks) wide_any |= k.c > kProductDim;
+  if (wide_any) {
+    B.blk_tiles = tiles;
+    B.blk_tasks = tasks;
+    split_large(tiles, tasks, kProductDim, &B.tile_blk);
+  }
+  const int nt_ = (int)tiles.size();
   // largest output blocks first (longest work items start early)
-  std::vector<int> order(nb);
-  for (int i = 0; i < nb; ++i) order[i] = i;
+  std::vector<int> order(nt_);
+  for (int i = 0; i < nt_; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     double wa = 0, wb = 0;
     for (int k = tiles[a].t0; k < tiles[a].t1; ++k) wa += task_flops(tasks[k]) / std::max(1, tiles[a].a);
@@ -1369,9 +1372,19 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   split_work(tiles, tasks, order, lists);
   B.mwork.upload_lists(lists, s);
   const bool wide = has_wide(tiles, tasks);
-  for (int y = 0; y < nb; ++y) {
+  // algorithmic flops per variant: an output block's unsplit tasks, counted
+  // with its first slice (the slices of a block run in one variant: a split
+  // product has wide tiles, so every tile runs on the 128-wide kernel)
+  std::vector<double> blk_fl(B.tile_blk.empty() ? 0 : B.blk_tiles.size(), 0.0);
+  for (size_t y = 0; y < blk_fl.size(); ++y)
+    for (int k = B.blk_tiles[y].t0; k < B.blk_tiles[y].t1; ++k) blk_fl[y] += task_flops(B.blk_tasks[k]);
+  for (int y = 0; y < nt_; ++y) {
     double fl = 0.0;
-    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
+    if (B.tile_blk.empty()) {
+      for (int k = tiles[y].t0; k < tiles[y].t1; ++k) fl += task_flops(tasks[k]);
+    } else if (y == 0 || B.tile_blk[y] != B.tile_blk[y - 1]) {
+      fl = blk_fl[B.tile_blk[y]];
+    }
     const int v = launch_variant(tiles[y], tasks, wide);
     B.vflops[v] += fl;
     // what the FP64/FP32 kernel issues: per active 16-row wave, 4 ceil(c/16)
@@ -1390,7 +1403,6 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   }
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "task table too large");
   B.n_tiles = nb;
-  B.n_tasks = (int64_t)tasks.size();
   B.n_dtasks = (int64_t)dtasks.size();
   double psi_elems = (double)B.n_elem;
   B.bytes[0] = 8.0 * (op_elems + 2 * psi_elems);
@@ -1738,18 +1750,20 @@ extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, in
   HCHECK(hipSetDevice(ctx->device));
   const std::vector<Tile>& tiles = b->h_tiles;
   const std::vector<Task>& tasks = b->h_tasks;
-  const int nb = (int)tiles.size();
-  std::vector<double> fl(nb, 0.0), rowfl(nb, 0.0);
-  for (int y = 0; y < nb; ++y)
-    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) {
-      fl[y] += task_flops(tasks[k]);
-      rowfl[y] += task_flops(tasks[k]) / std::max(1, tiles[y].a);
-    }
-  std::vector<int> byfl(nb);
-  for (int i = 0; i < nb; ++i) byfl[i] = i;
+  // owners per output block (a block split into column slices for the
+  // product stays on one rank), weighed by its unsplit tasks
+  const bool sliced = !b->blk_tiles.empty();
+  const std::vector<Tile>& btiles = sliced ? b->blk_tiles : tiles;
+  const std::vector<Task>& btasks = sliced ? b->blk_tasks : tasks;
+  const int nblk = (int)btiles.size(), nt = (int)tiles.size();
+  std::vector<double> fl(nblk, 0.0);
+  for (int y = 0; y < nblk; ++y)
+    for (int k = btiles[y].t0; k < btiles[y].t1; ++k) fl[y] += task_flops(btasks[k]);
+  std::vector<int> byfl(nblk);
+  for (int i = 0; i < nblk; ++i) byfl[i] = i;
   std::stable_sort(byfl.begin(), byfl.end(), [&](int x, int y) { return fl[x] > fl[y]; });
   std::vector<double> load(nranks, 0.0);
-  std::vector<int> owner(nb, 0);
+  std::vector<int> owner(nblk, 0);
   for (int y : byfl) {
     int r = 0;
     for (int j = 1; j < nranks; ++j)
@@ -1757,13 +1771,16 @@ extern "C" int heff_blocks_shard(heff_ctx* ctx, heff_blocks* b, int32_t rank, in
     owner[y] = r;
     load[r] += fl[y];
   }
-  // the full product's block order (largest per-row work first), restricted
-  std::vector<int> order(nb);
-  for (int i = 0; i < nb; ++i) order[i] = i;
+  // the full product's tile order (largest per-row work first), restricted
+  std::vector<double> rowfl(nt, 0.0);
+  for (int y = 0; y < nt; ++y)
+    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) rowfl[y] += task_flops(tasks[k]) / std::max(1, tiles[y].a);
+  std::vector<int> order(nt);
+  for (int i = 0; i < nt; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return rowfl[x] > rowfl[y]; });
   std::vector<int> mine;
   for (int y : order)
-    if (owner[y] == rank) mine.push_back(y);
+    if (owner[sliced ? b->tile_blk[y] : y] == rank) mine.push_back(y);
   std::vector<Work> lists[kNumVariants];
   split_work(tiles, tasks, mine, lists);
   HCHECK(hipStreamSynchronize(ctx->stream));  // no product still reads the old lists
@@ -2782,12 +2799,14 @@ static void make_grad_plan(const heff_blocks& B, int side, hipStream_t s) {
   std::map<std::pair<int, int64_t>, int> tile_of;
   std::vector<Tile> tiles;
   std::vector<std::vector<Task>> per;
-  const int nb = (int)B.h_tiles.size();
+  const std::vector<Tile>& btiles = B.blk_tiles.empty() ? B.h_tiles : B.blk_tiles;
+  const std::vector<Task>& btasks = B.blk_tiles.empty() ? B.h_tasks : B.blk_tasks;
+  const int nb = (int)btiles.size();
   for (int y = 0; y < nb; ++y) {
-    const Tile& ty = B.h_tiles[y];
+    const Tile& ty = btiles[y];
     const int64_t py = ty.offOut;  // psi_y block (a x e, row stride e)
     for (int k = ty.t0; k < ty.t1; ++k) {
-      const Task& t = B.h_tasks[k];
+      const Task& t = btasks[k];
       const uint32_t fl = t.flags;
       const bool tl = fl & T_TL, tx = fl & T_TX, tr = fl & T_TR;
       if (left ? (fl & T_IDL) : (fl & T_IDR)) continue;
@@ -2879,7 +2898,7 @@ static void make_grad_plan(const heff_blocks& B, int side, hipStream_t s) {
     tiles[i].t1 = (int32_t)tasks.size();
   }
   if (tasks.size() > (size_t)INT32_MAX) throw Error(HEFF_EINVAL, "gradient task table too large");
-  split_large(tiles, tasks);
+  split_large(tiles, tasks, kMaxDim);
   std::vector<int> order(tiles.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::vector<double> cost(tiles.size(), 0.0);

@@ -88,7 +88,7 @@ struct DevWorkSet {
 
 // product planning and launch helpers (heff_host.hip)
 int tile_dim(const Tile& t, const std::vector<Task>& tasks);
-void split_wide_c(std::vector<Tile>& tiles, std::vector<Task>& tasks);
+bool split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks, int max_dim, std::vector<int>* parent = nullptr);
 double task_flops(const Task& t);
 void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks, const std::vector<int>& order,
                 std::vector<Work> (&lists)[kNumVariants], const std::vector<int>* key = nullptr);

@@ -11,6 +11,11 @@ namespace heff {
 // largest output width and inner dimension one task may have in the
 // matrix-core kernels (larger blocks are split into several tasks / tiles)
 constexpr int kMaxDim = 256;
+// largest output width and middle dimension of the Davidson product's
+// tasks: wider output blocks run as column slices and wider middle
+// dimensions as consecutive ranges, so the product never needs the
+// 256-wide kernel instances (one work-group per CU, register spills)
+constexpr int kProductDim = 128;
 
 // One block task of the chained product  out += f * op(L) * op(X) * op(R).
 // Shapes: out a x e, op(L) a x b, op(X) b x c, op(R) c x e.  op(M) is M or

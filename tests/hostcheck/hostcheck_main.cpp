@@ -259,6 +259,28 @@ int main(int argc, char** argv) {
       if ((rc = heff_apply(ctx, b, HEFF_FP32, x, y))) return fail(ctx, "heff_apply FP32", rc);
       if ((rc = heff_apply(ctx, b, HEFF_BF16X3, x, y))) return fail(ctx, "heff_apply BF16X3", rc);
       if ((rc = heff_diag(ctx, b, (double*)y))) return fail(ctx, "heff_diag", rc);
+      // each rank's share of a three-way output-block shard, then the full
+      // product's lists again
+      for (int rk = 0; rk < 3; ++rk) {
+        double sf = 0.0;
+        if ((rc = heff_blocks_shard(ctx, b, rk, 3, &sf))) return fail(ctx, "heff_blocks_shard", rc);
+        if ((rc = heff_apply(ctx, b, HEFF_FP64, x, y))) return fail(ctx, "heff_apply of a shard", rc);
+      }
+      if ((rc = heff_blocks_shard(ctx, b, 0, 1, nullptr))) return fail(ctx, "heff_blocks_shard (full)", rc);
+      {  // operand gradients (their task tables take the output blocks whole)
+        void* ap[4] = {};
+        int64_t an[4] = {};
+        if ((rc = heff_op_arena(b, HEFF_FP64, ap, an))) return fail(ctx, "heff_op_arena", rc);
+        void *dL = nullptr, *dR = nullptr, *dpsi = nullptr;
+        hipMalloc(&dL, (size_t)std::max<int64_t>(an[0] + an[1], 1) * 8);
+        hipMalloc(&dR, (size_t)std::max<int64_t>(an[2] + an[3], 1) * 8);
+        hipMalloc(&dpsi, (size_t)ne * 8);
+        if ((rc = heff_energy_backward(ctx, b, HEFF_FP64, x, 1.0, dpsi, dL, dR)))
+          return fail(ctx, "heff_energy_backward", rc);
+        hipFree(dL);
+        hipFree(dR);
+        hipFree(dpsi);
+      }
       if (probs[i]->n - (probs[i]->n / 2 - 1) - 2 >= 1) {  // a sweep step to the next pair, then its product
         heff_blocks* b2 = nullptr;
         heff_trunc* tr = nullptr;

@@ -128,6 +128,45 @@ def test_backward_full_size_n40_d4096(heff, ctx):
     assert checked >= 4
     assert B.energy(x) == e0
 
+def test_backward_wide_blocks_n14_d1024_beta1(heff, ctx):
+    # blocks up to 170 wide, which the product runs as column slices and
+    # ranges of the middle dimension, while the operand gradients take each
+    # output block whole: dE/dpsi = 2 H_eff psi, psi . dE/dpsi = 2E, and unit
+    # steps of single arena entries (E is linear in each) change E by the
+    # reported gradient, on both sides
+    p = synth.make_problem(14, 1024, 2, beta=1.0)
+    print("case backward wide blocks N=14 D=1024 seed=2 beta=1", flush=True)
+    assert max(max(b[4], b[5]) for b in synth.psi_blocks(p)) > 128
+    B = heff.Blocks(ctx, p)
+    x = _dev(synth.random_psi(p))
+    hx = torch.empty_like(x)
+    B.apply(x, hx)
+    e0 = B.energy(x)
+    dpsi, dL, dR = B.energy_backward(x)
+    assert float((dpsi - 2 * hx).norm()) <= 1e-11 * float(hx.norm())
+    assert abs(float(x @ dpsi) - 2 * e0) <= 1e-10 * abs(e0)
+    views = B.op_arena(heff.FP64)
+    n = [v.numel() for v in views]
+    grads = [dL[:n[0]], dL[n[0]:n[0] + n[1]], dR[:n[2]], dR[n[2]:n[2] + n[3]]]
+    rng = np.random.default_rng(13)
+    checked = 0
+    for v, gv in zip(views, grads):
+        if v.numel() == 0:
+            continue
+        nz = torch.nonzero(gv).flatten().cpu().numpy()
+        for i in (rng.choice(nz, min(3, len(nz)), replace=False) if len(nz) else []):
+            i = int(i)
+            old = float(v[i].item())
+            v[i] = old + 1.0
+            e1 = B.energy(x)
+            v[i] = old
+            g = float(gv[i].item())
+            assert abs((e1 - e0) - g) <= 1e-10 * max(1.0, abs(e0)), (i, e1 - e0, g)
+            checked += 1
+    assert checked >= 6
+    assert B.energy(x) == e0
+
+
 def test_fp32_gradients_track_fp64(heff, case8):
     p, B, psi = case8
     print("case backward fp32 N=8 D=32 seed=5", flush=True)

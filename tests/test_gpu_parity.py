@@ -91,13 +91,15 @@ def test_davidson_full_size_properties_n40_d4096(heff, ctx):
     assert abs(r - rn) <= 1e-8 * abs(ths[-1])
 
 
-@pytest.mark.parametrize("N,D,seed,P", [(12, 96, 12, 3), (16, 256, 21, 4)])
-def test_shards_partition_the_product_bitwise(heff, ctx, N, D, seed, P):
+@pytest.mark.parametrize("N,D,seed,P,beta", [(12, 96, 12, 3, 0.5), (16, 256, 21, 4, 0.5), (14, 1024, 2, 3, 1.0)])
+def test_shards_partition_the_product_bitwise(heff, ctx, N, D, seed, P, beta):
     # one GPU's share of an output-block-sharded product: the P shards write
     # disjoint sets of whole output blocks whose union is the full product,
-    # bit for bit, and their flops add up to the product's
-    print("case shards N=%d D=%d seed=%d P=%d" % (N, D, seed, P), flush=True)
-    p = synth.make_problem(N, D, seed)
+    # bit for bit, and their flops add up to the product's (the last case
+    # has blocks wider than 128, which the product runs as column slices:
+    # a block's slices stay on one rank)
+    print("case shards N=%d D=%d seed=%d P=%d beta=%g" % (N, D, seed, P, beta), flush=True)
+    p = synth.make_problem(N, D, seed, beta=beta)
     B = heff.Blocks(ctx, p)
     x = _dev(synth.random_psi(p))
     full = torch.empty_like(x)
@@ -275,17 +277,19 @@ WIDE_BARS = (5e-5, 5e-5)
 
 
 def test_apply_wide_variants_match_oracle(heff, ctx):
-    # Random isometries at a size whose blocks reach the 128- and 256-wide
-    # kernel variants (N=14, D=1024, beta=1: sectors up to 170 wide; outputs
-    # at most 128 wide with tasks of a middle dimension above 128 run those
-    # tasks split into ranges of it), the whole output element by element
+    # Random isometries at a size whose blocks are wider than 128 (N=14,
+    # D=1024, beta=1: sectors up to 170 wide): the product runs such output
+    # blocks as column slices and middle dimensions above 128 as ranges of
+    # it, all on the 128-wide kernel (the block build's renormalization
+    # still takes the 256-wide one); the whole output element by element
     # against O-BLOCK; FP32 and the bf16 split against the same oracle
     # output.
     p = synth.make_problem(14, 1024, 2, beta=1.0)
     print("case N=14 D=1024 seed=2 beta=1 random isometries", flush=True)
+    assert max(max(b[4], b[5]) for b in synth.psi_blocks(p)) > 128
     B = heff.Blocks(ctx, p, precs=(heff.FP64, heff.FP32, heff.BF16X3))
     vst = B.variant_stats()
-    assert vst[2][1] > 0 and vst[3][1] > 0, vst
+    assert vst[2][1] > 0 and vst[3][1] == 0, vst
     psi = synth.random_psi(p)
     y = torch.empty(B.n_elem, dtype=torch.float64, device="cuda")
     B.apply(_dev(psi), y)
@@ -309,7 +313,7 @@ def test_mixed_precision_davidson_energy(heff, ctx, prec, N, D, seed, beta):
     # same tolerance or its noise floor (once ||r|| <= 1e-4 |theta|, 12
     # steps without a new smallest residual below 0.8 of the best) and must
     # stop there, not at the step cap.
-    # The second case reaches the 128- and 256-wide kernel variants.
+    # The second case has blocks wider than 128 (run as column slices).
     p = synth.make_problem(N, D, seed, beta=beta)
     print("case N=%d D=%d seed=%d beta=%g prec %d" % (N, D, seed, beta, prec), flush=True)
     B = heff.Blocks(ctx, p, precs=(0, prec))
@@ -398,7 +402,7 @@ def test_full_size_sampled_rows_n40_d4096(heff, ctx, beta):
     for (_, _, _, _, da, db, off) in blocks:
         w = max(da, db)
         classes[0 if w <= 32 else 1 if w <= 64 else 2 if w <= 128 else 3].append((da, db, off))
-    # beta = 1 keeps wider sectors: blocks beyond 128 (the 256-wide kernels)
+    # beta = 1 keeps wider sectors: blocks beyond 128 (run as column slices)
     assert (len(classes[3]) > 0) == (beta == 1.0)
     idx = []
     for cl in classes:
@@ -569,22 +573,23 @@ def test_batch_matches_single_and_oracle(heff, ctx):
 
 
 def test_fp64_kernel_families_agree_bitwise(heff, ctx):
-    # N=24, D=4096 has blocks up to 194 wide (the 128- and 256-wide
-    # variants): the automatic choice runs the LDS-ring kernel; the
-    # register-staged kernel everywhere and the ring kernel everywhere must
-    # give the same product bit for bit (same sums in the same order),
-    # including the ring's dword fallback at buffer ends
+    # N=24, D=4096 has blocks up to 194 wide (run as column slices and
+    # ranges of the middle dimension on the 128-wide variant): the automatic
+    # choice runs the LDS-ring kernel; the register-staged kernel everywhere
+    # and the ring kernel everywhere must give the same product bit for bit
+    # (same sums in the same order), including the ring's dword fallback at
+    # buffer ends
     p = synth.make_problem(24, 4096, 2)
     print("case fp64 kernel families N=24 D=4096 seed=2", flush=True)
+    assert max(max(b[4], b[5]) for b in synth.psi_blocks(p)) > 128
     B = heff.Blocks(ctx, p)
     st = B.variant_stats()
-    assert st[2][1] > 0 and st[3][1] > 0  # 128- and 256-wide variants exist
+    assert st[2][1] > 0 and st[3][1] == 0
     x = torch.tensor(synth.random_psi(p), device="cuda")
     ys = []
     try:
         # FP64_RING_DWORD: the ring's dword loads everywhere, the path it
-        # takes where a 16-byte load could pass a buffer's end (a 256-wide
-        # step issues up to 2*16 + 8 of them per wave)
+        # takes where a 16-byte load could pass a buffer's end
         for mode in (heff.FP64_AUTO, heff.FP64_STAGED, heff.FP64_RING, heff.FP64_RING_DWORD):
             ctx.set_fp64_kernel(mode)
             y = torch.empty_like(x)

@@ -80,9 +80,9 @@ def test_su2_product_medium_all_precisions(heff, ctx):
 
 
 def test_su2_product_wide_middle_dimension(heff, ctx):
-    # right sectors up to 200 wide beside narrow ones: outputs at most 128
-    # wide whose tasks have a middle dimension above 128 (the 256-wide
-    # kernel instance); element-wise vs the task form
+    # right sectors up to 200 wide beside narrow ones: outputs wider than
+    # 128 (run as column slices) and tasks with a middle dimension above 128
+    # (run as ranges of it); element-wise vs the task form
     rng = np.random.default_rng(10)
     Ls = S.sectors(rng, range(2, 5), 3, 24, 4)
     Rs = [(2, 0, 200), (2, 2, 40), (3, 1, 150), (3, 3, 20), (4, 0, 90), (4, 2, 130)]
