@@ -1252,7 +1252,11 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   const int nb = (int)B.blk_off.size();
   std::vector<std::vector<Task>> per(nb);
   std::vector<std::vector<DiagTask>> dper(nb);
-  std::set<std::pair<int, int64_t>> seen;  // referenced operator blocks (store id, offset)
+  // referenced operator blocks: store (0, 1 left store and temporaries; 2,
+  // 3 right) in the top bits, element offset below
+  std::unordered_set<uint64_t> seen;
+  seen.reserve(1u << 16);
+  auto first_use = [&](int store, int64_t off) { return seen.insert(((uint64_t)store << 60) | (uint64_t)off).second; };
   double op_elems = 0.0;
   for (const Term& tm : B.terms) {
     const Store* lst = tm.l.where < 0 ? nullptr : (tm.l.where == 0 ? &Ls : &Lt);
@@ -1300,7 +1304,7 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
           t.ldL = (uint16_t)lst->lay(tm.l.id).cols[lblk];
           if (tm.l.trans) fl |= T_TL;
           if (tm.l.where == 1) fl |= T_SELL;
-          if (seen.insert({tm.l.where, t.offL}).second) op_elems += (double)t.a * t.b;
+          if (first_use(tm.l.where, t.offL)) op_elems += (double)t.a * t.b;
         }
         if (!rst) fl |= T_IDR;
         else {
@@ -1308,7 +1312,7 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
           t.ldR = (uint16_t)rst->lay(tm.r.id).cols[rblk];
           if (!tm.r.trans) fl |= T_TR;
           if (tm.r.where == 1) fl |= T_SELR;
-          if (seen.insert({2 + tm.r.where, t.offR}).second) op_elems += (double)t.c * t.e;
+          if (first_use(2 + tm.r.where, t.offR)) op_elems += (double)t.c * t.e;
         }
         t.flags = (uint16_t)fl;
         per[y].push_back(t);
@@ -1362,12 +1366,10 @@ static void build_tasks(heff_blocks& B, hipStream_t s) {
   // largest output blocks first (longest work items start early)
   std::vector<int> order(nt_);
   for (int i = 0; i < nt_; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    double wa = 0, wb = 0;
-    for (int k = tiles[a].t0; k < tiles[a].t1; ++k) wa += task_flops(tasks[k]) / std::max(1, tiles[a].a);
-    for (int k = tiles[b].t0; k < tiles[b].t1; ++k) wb += task_flops(tasks[k]) / std::max(1, tiles[b].a);
-    return wa > wb;
-  });
+  std::vector<double> rowfl(nt_, 0.0);
+  for (int y = 0; y < nt_; ++y)
+    for (int k = tiles[y].t0; k < tiles[y].t1; ++k) rowfl[y] += task_flops(tasks[k]) / std::max(1, tiles[y].a);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return rowfl[a] > rowfl[b]; });
   std::vector<Work> lists[kNumVariants];
   split_work(tiles, tasks, order, lists);
   B.mwork.upload_lists(lists, s);

@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <set>
+#include <unordered_set>
 #include <stdexcept>
 #include <string>
 #include <thread>
