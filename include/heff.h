@@ -452,6 +452,11 @@ int heff_dav_free(heff_dav* d);
  * heff_build_blocks (FP64 always; bits HEFF_FP32 / HEFF_BF16X3 add FP32
  * operand copies).  heff_su2_apply(): out = H psi on the context's stream
  * (device vectors of n_elem elements of the precision's type, no alias).
+ * The handle owns the partial sums of the output blocks whose task chains
+ * run split over several work-groups (allocated by heff_su2_create), so
+ * two products with one handle must not overlap: call them on one stream.
+ * Results are deterministic (fixed summation order) but not bitwise equal
+ * to an unsplit accumulation.
  * heff_su2_stats(): tasks, algorithmic flops per product (the U(1) count
  * per task) and the number of magnetic-resolved amplitudes the reduced
  * vector stands for at M = S_tot (sum over blocks of rows x cols x the

@@ -489,19 +489,90 @@ bool has_wide(const std::vector<Tile>& tiles, const std::vector<Task>& tasks) {
 // overhead (loads, LDS traffic, barrier) of about kStepCost instructions
 // plus its matrix work, 4 ceil(c/16) instructions per stage-1 step and 4 NE
 // per stage-2 step (NE = the output-width bucket of the kernel instance).
-static double item_cost(const Tile& tile, const std::vector<Task>& tasks, int v) {
-  constexpr double kStepCost = 8.0;
-  const int nt = 2 << v;
+static int width_bucket(const Tile& tile, int nt) {
   const int ne = (tile.e + 15) / 16;
-  int neb = nt;
   for (int q = 1; q <= 3; ++q)
-    if (ne <= std::max(1, nt * q / 4)) { neb = std::max(1, nt * q / 4); break; }
+    if (ne <= std::max(1, nt * q / 4)) return std::max(1, nt * q / 4);
+  return nt;
+}
+static double task_cost(const Task& t, int nt, int neb) {
+  constexpr double kStepCost = 8.0;
+  const int nb = (t.b + 15) / 16, nc = (t.c + 15) / 16;
+  return nb * (kStepCost + 4.0 * std::min(nc, nt)) + nc * (kStepCost + 4.0 * neb);
+}
+static double item_cost(const Tile& tile, const std::vector<Task>& tasks, int v) {
+  const int nt = 2 << v, neb = width_bucket(tile, nt);
   double cost = 0.0;
-  for (int k = tile.t0; k < tile.t1; ++k) {
-    const int nb = (tasks[k].b + 15) / 16, nc = (tasks[k].c + 15) / 16;
-    cost += nb * (kStepCost + 4.0 * std::min(nc, nt)) + nc * (kStepCost + 4.0 * neb);
-  }
+  for (int k = tile.t0; k < tile.t1; ++k) cost += task_cost(tasks[k], nt, neb);
   return cost;
+}
+
+// Split the task chains of the tiles whose work items would each take
+// longer than the average work-group slot (total estimated work over
+// `slots` concurrent work-groups): such a tile's tasks are cut into P <=
+// max_parts contiguous ranges of about equal estimated time, each range a
+// tile of its own that writes its partial sum (a x e, row stride e) into
+// the output buffer at part_base and beyond; jobs then add the parts into
+// the tile's output block in order.  The longest chain no longer bounds the
+// product's time, at the price of P partial blocks and one small
+// reduction.  Returns the number of part elements after part_base.
+int64_t split_chains(std::vector<Tile>& tiles, const std::vector<Task>& tasks, int slots, int max_parts,
+                     int64_t part_base, std::vector<RedJob>& jobs) {
+  jobs.clear();
+  const bool wide = has_wide(tiles, tasks);
+  const size_t n = tiles.size();
+  std::vector<double> cost(n);
+  double total = 0.0;
+  for (size_t t = 0; t < n; ++t) {
+    cost[t] = item_cost(tiles[t], tasks, launch_variant(tiles[t], tasks, wide));
+    total += cost[t] * std::max(1, (tiles[t].a + kTileRows - 1) / kTileRows);
+  }
+  const double target = total / std::max(1, slots);
+  std::vector<Tile> nt;
+  nt.reserve(n);
+  int64_t part_elems = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const Tile& tl = tiles[t];
+    const int ntask = tl.t1 - tl.t0;
+    const int P = std::min(ntask, (int)std::min<double>(max_parts, std::ceil(cost[t] / std::max(target, 1.0))));
+    if (P < 2 || tl.a <= 0 || tl.e <= 0) {
+      nt.push_back(tl);
+      continue;
+    }
+    const int v = launch_variant(tl, tasks, wide), ntv = 2 << v, neb = width_bucket(tl, ntv);
+    const int64_t blk = (int64_t)tl.a * tl.e;
+    RedJob j{};
+    j.out_off = tl.offOut;
+    j.part_off = part_base + part_elems;
+    j.a = tl.a;
+    j.e = tl.e;
+    j.ld = tl.ldOut;
+    int k = tl.t0;
+    double done = 0.0;
+    int made = 0;
+    for (int p = 0; p < P; ++p) {
+      Tile u = tl;
+      u.t0 = k;
+      if (p == P - 1) {
+        k = tl.t1;
+      } else {
+        // at least one task per part, and leave one for each later part
+        const double goal = cost[t] * (p + 1) / P;
+        do done += task_cost(tasks[k], ntv, neb), ++k;
+        while (k < tl.t1 - (P - 1 - p) && done + 0.5 * task_cost(tasks[k], ntv, neb) < goal);
+      }
+      u.t1 = k;
+      u.offOut = part_base + part_elems + (int64_t)made * blk;
+      u.ldOut = tl.e;
+      nt.push_back(u);
+      ++made;
+    }
+    j.parts = made;
+    part_elems += (int64_t)made * blk;
+    jobs.push_back(j);
+  }
+  tiles.swap(nt);
+  return part_elems;
 }
 
 void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks, const std::vector<int>& order,

@@ -89,6 +89,8 @@ struct DevWorkSet {
 
 // product planning and launch helpers (heff_host.hip)
 int tile_dim(const Tile& t, const std::vector<Task>& tasks);
+int64_t split_chains(std::vector<Tile>& tiles, const std::vector<Task>& tasks, int slots, int max_parts,
+                     int64_t part_base, std::vector<RedJob>& jobs);
 bool split_large(std::vector<Tile>& tiles, std::vector<Task>& tasks, int max_dim, std::vector<int>* parent = nullptr);
 double task_flops(const Task& t);
 void split_work(const std::vector<Tile>& tiles, const std::vector<Task>& tasks, const std::vector<int>& order,

@@ -55,6 +55,15 @@ struct Tile {
 };
 static_assert(sizeof(Tile) == 32, "tile layout");
 
+// Fixed-order sum of the parts of one split task chain: out block (a x e at
+// out_off, row stride ld) = sum over p < parts of the part p (a x e, row
+// stride e) at part_off + p a e, added in the order of p (the parts are
+// written by tiles of their own, like any output block, behind psi').
+struct RedJob {
+  int64_t out_off, part_off;
+  int32_t a, e, ld, parts;
+};
+
 // One work-group's share: rows [row0, row0 + ROWS) of tile `tile`.
 struct Work {
   int32_t tile;
@@ -183,6 +192,8 @@ hipError_t launch_row_norms(const int64_t* boff, const int32_t* m, const int32_t
 // left singular vectors as isometry columns, each signed so that its
 // largest-magnitude entry is positive (GatherJob.cols holds row indices of W^T)
 hipError_t launch_gather_rows(const GatherJob* jobs, int n_jobs, const double* WT, double* out, hipStream_t s);
+hipError_t launch_reduce_parts_f64(const RedJob* jobs, int n_jobs, const double* part, double* out, hipStream_t s);
+hipError_t launch_reduce_parts_f32(const RedJob* jobs, int n_jobs, const float* part, float* out, hipStream_t s);
 hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0,
                        const double* L1, const double* R0, const double* R1, double* out,
                        hipStream_t s);

@@ -1358,6 +1358,36 @@ __global__ __launch_bounds__(256) void diag_kernel(const Tile* __restrict__ tile
   }
 }
 
+// ------------------------------------------------------------------ split task chains
+// One work-group column per job, blockIdx.y strides over its elements; each
+// output element is the sum of its parts in the order of p (deterministic).
+// The parts and the output may share one buffer (disjoint ranges).
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const RedJob* __restrict__ jobs, const T* part, T* out) {
+  const RedJob j = jobs[blockIdx.x];
+  const int64_t n = (int64_t)j.a * j.e;
+  for (int64_t i = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.y * blockDim.x) {
+    const T* p = part + j.part_off + i;
+    T s = p[0];
+    for (int q = 1; q < j.parts; ++q) s += p[q * n];
+    const int64_t r = i / j.e, c = i - r * j.e;
+    out[j.out_off + r * j.ld + c] = s;
+  }
+}
+
+template <typename T>
+static hipError_t launch_reduce_parts(const RedJob* jobs, int n_jobs, const T* part, T* out, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_parts_kernel<T>, dim3((unsigned)n_jobs, 16), dim3(256), 0, s, jobs, part, out);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_parts_f64(const RedJob* jobs, int n_jobs, const double* part, double* out, hipStream_t s) {
+  return launch_reduce_parts<double>(jobs, n_jobs, part, out, s);
+}
+hipError_t launch_reduce_parts_f32(const RedJob* jobs, int n_jobs, const float* part, float* out, hipStream_t s) {
+  return launch_reduce_parts<float>(jobs, n_jobs, part, out, s);
+}
+
 hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0,
                        const double* L1, const double* R0, const double* R1, double* out, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;

@@ -192,6 +192,11 @@ struct heff_su2 {
   heff::DevBuf dL, dR, fL, fR;  // FP64 arenas and FP32 copies of the reduced operator blocks
   heff::DevBuf d_tiles, d_tasks;
   heff::DevWorkSet mwork;
+  // split task chains: the product writes psi' and then the chains' partial
+  // sums into a work vector (FP64; FP32 for the FP32 and bf16-split
+  // products), the jobs add the parts into psi', which is copied out
+  heff::DevBuf d_red, work64, work32;
+  int n_red = 0;
   int64_t n_tasks = 0;
   double flops = 0.0, n_resolved = 0.0;
 };
@@ -352,6 +357,12 @@ static void build(heff_ctx* ctx, const heff_su2_problem* p, uint32_t prec_mask, 
   // right sectors up to 256 wide: FP64 233 -> 140 ms, FP32 110 -> 88 ms,
   // bf16 split 112 -> 79 ms on one box)
   split_large(tiles, tasks, kProductDim);
+  // the longest output blocks gather thousands of tasks: their chains are
+  // split over several work-groups (partial sums, then a fixed-order sum)
+  // so that no chain outlasts the average work-group slot of the 128-wide
+  // kernel (256 CUs, two work-groups each)
+  std::vector<RedJob> jobs;
+  const int64_t part_elems = split_chains(tiles, tasks, 512, 8, H.n_elem, jobs);
   const int nt_ = (int)tiles.size();
   std::vector<int> order(nt_);
   for (int i = 0; i < nt_; ++i) order[i] = i;
@@ -361,6 +372,13 @@ static void build(heff_ctx* ctx, const heff_su2_problem* p, uint32_t prec_mask, 
   H.mwork.upload_lists(lists, s);
   upload(H.d_tiles, tiles, s);
   upload(H.d_tasks, tasks, s);
+  H.n_red = (int)jobs.size();
+  if (H.n_red) {
+    upload(H.d_red, jobs, s);
+    const size_t nw = (size_t)(H.n_elem + part_elems);
+    H.work64.alloc(nw * sizeof(double));
+    if (prec_mask & ((1u << HEFF_FP32) | (1u << HEFF_BF16X3))) H.work32.alloc(nw * sizeof(float));
+  }
   upload(H.dL, L.data, s);
   upload(H.dR, R.data, s);
   H.prec_mask = prec_mask | (1u << HEFF_FP64);
@@ -423,7 +441,24 @@ extern "C" int heff_su2_apply(heff_ctx* ctx, const heff_su2* h, int prec, const 
   Bases<float> b32{};
   b32.L[0] = b32.L[1] = h->fL.as<float>();
   b32.R[0] = b32.R[1] = h->fR.as<float>();
-  run_product(ctx, h->d_tiles.as<Tile>(), h->d_tasks.as<Task>(), h->mwork.ws, prec, h->prec_mask, b64, b32, psi, out);
+  if (!h->n_red) {
+    run_product(ctx, h->d_tiles.as<Tile>(), h->d_tasks.as<Task>(), h->mwork.ws, prec, h->prec_mask, b64, b32, psi, out);
+  } else {
+    // into the work vector; after the variants joined the context stream,
+    // the parts are added into psi' and psi' is copied out
+    const bool f64 = prec == HEFF_FP64;
+    void* w = f64 ? h->work64.p : h->work32.p;
+    if (!w) throw Error(HEFF_ENOTSUP, "precision not built for this SU(2) problem");
+    run_product(ctx, h->d_tiles.as<Tile>(), h->d_tasks.as<Task>(), h->mwork.ws, prec, h->prec_mask, b64, b32, psi, w);
+    if (f64)
+      HCHECK(launch_reduce_parts_f64(h->d_red.as<RedJob>(), h->n_red, h->work64.as<double>(), h->work64.as<double>(),
+                                     ctx->stream));
+    else
+      HCHECK(launch_reduce_parts_f32(h->d_red.as<RedJob>(), h->n_red, h->work32.as<float>(), h->work32.as<float>(),
+                                     ctx->stream));
+    HCHECK(hipMemcpyAsync(out, w, (size_t)h->n_elem * (f64 ? sizeof(double) : sizeof(float)), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
   ABI_END(ctx)
 }
 

@@ -173,7 +173,7 @@ static void check_chain(const heff::Tile* tiles, const heff::WorkSet& ws, const 
       if (tile.ldOut < tile.e) violation("tile %d: output stride %d below width %d", w.tile, tile.ldOut, tile.e);
       if (tile.a > 0 && tile.e > 0) {
         const int64_t last = tile.offOut + (int64_t)(tile.a - 1) * tile.ldOut + tile.e;
-        if (!b.out || !inside(b.out, (size_t)last * sizeof(T)))
+        if (!b.out || tile.offOut < 0 || !inside(b.out, (size_t)last * sizeof(T)))
           violation("tile %d: output elements [%lld, %lld) outside the output buffer", w.tile,
                     (long long)tile.offOut, (long long)last);
       }
@@ -328,6 +328,32 @@ hipError_t launch_mfma_batch_f32(const Tile* tiles, const WorkSet& ws, const Tas
       return b;
     });
   });
+}
+
+template <typename T>
+static hipError_t checked_reduce(const RedJob* jobs, int n_jobs, const T* part, T* out) {
+  return hc::run([=]() {
+    if (n_jobs <= 0) return;
+    if (!hc::check_range(jobs, (size_t)n_jobs * sizeof(RedJob), "reduction jobs")) return;
+    for (int i = 0; i < n_jobs; ++i) {
+      const RedJob j = jobs[i];
+      ++hc::g_items;
+      if (j.a <= 0 || j.e <= 0 || j.parts < 2 || j.ld < j.e || j.out_off < 0 || j.part_off < 0) {
+        hc::violation("reduction job %d: a=%d e=%d ld=%d parts=%d", i, j.a, j.e, j.ld, j.parts);
+        continue;
+      }
+      const int64_t last = j.out_off + (int64_t)(j.a - 1) * j.ld + j.e;
+      if (!out || !hc::inside(out, (size_t)last * sizeof(T))) hc::violation("reduction job %d: output outside", i);
+      const int64_t plast = j.part_off + (int64_t)j.parts * j.a * j.e;
+      if (!part || !hc::inside(part, (size_t)plast * sizeof(T))) hc::violation("reduction job %d: parts outside", i);
+    }
+  });
+}
+hipError_t launch_reduce_parts_f64(const RedJob* jobs, int n_jobs, const double* part, double* out, hipStream_t) {
+  return checked_reduce(jobs, n_jobs, part, out);
+}
+hipError_t launch_reduce_parts_f32(const RedJob* jobs, int n_jobs, const float* part, float* out, hipStream_t) {
+  return checked_reduce(jobs, n_jobs, part, out);
 }
 
 hipError_t launch_diag(const Tile* tiles, int64_t n_tiles, const DiagTask* tasks, const double* L0, const double* L1,

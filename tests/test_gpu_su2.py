@@ -99,12 +99,15 @@ def test_su2_product_wide_middle_dimension(heff, ctx):
 
 def test_su2_product_benchmark_size_sampled(heff, ctx):
     # the benchmark problem (75 sectors, 2692 multiplets per block, 1500
-    # terms): output blocks sampled (the two largest and six random)
+    # terms): output blocks sampled (the two largest, whose task chains run
+    # split over several work-groups, and six random); a second product is
+    # bitwise the first (the split chains' parts are added in a fixed order)
     p = S.bench_problem(3)
     print("case benchmark size", flush=True)
     H = heff.Su2(ctx, p)
     x = S.random_psi(p, seed=5)
     y = _run(heff, H, x, heff.FP64)
+    assert np.array_equal(_run(heff, H, x, heff.FP64), y)
     blocks = S.psi_blocks(p)
     rng = np.random.default_rng(0)
     pick = sorted(blocks, key=lambda b: -b[2] * b[3])[:2] + [blocks[i] for i in rng.choice(len(blocks), 6, replace=False)]
