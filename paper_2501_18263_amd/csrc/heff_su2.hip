@@ -359,10 +359,13 @@ static void build(heff_ctx* ctx, const heff_su2_problem* p, uint32_t prec_mask, 
   split_large(tiles, tasks, kProductDim);
   // the longest output blocks gather thousands of tasks: their chains are
   // split over several work-groups (partial sums, then a fixed-order sum)
-  // so that no chain outlasts the average work-group slot of the 128-wide
-  // kernel (256 CUs, two work-groups each)
+  // into parts of at most a quarter of the average work-group slot of the
+  // 128-wide kernel (256 CUs, two work-groups each), which leaves the
+  // longest-first queues room to balance (benchmark problem, FP64 / FP32 /
+  // bf16 split: 512 slots and 8 parts 105 / 60 / 53 ms, 1024 and 8 100 /
+  // 51 / 41 ms, 2048 and 16 99 / 50 / 42 ms on one box)
   std::vector<RedJob> jobs;
-  const int64_t part_elems = split_chains(tiles, tasks, 512, 8, H.n_elem, jobs);
+  const int64_t part_elems = split_chains(tiles, tasks, 2048, 16, H.n_elem, jobs);
   const int nt_ = (int)tiles.size();
   std::vector<int> order(nt_);
   for (int i = 0; i < nt_; ++i) order[i] = i;
